@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark: the fused 8th-order acoustic stencil on one MI355X.
+
+One benchmark "step" is one whole forward shot of the 512^3 workload: reset
+(zero both wavefields) then 1000 fused time steps with the 20-node sponge, the
+Ricker point source and the 512x512 receiver plane sampled every step.  All
+inputs (velocity, wavelet) are resident in HBM before timing starts.
+
+value = grid points x time steps / wall time (Gpts/s) over the timed shots.
+roofline: algorithmic bytes of one fused step (16 B per point: read A^n,
+A^{n-1}, m; write A^{n+1}) / the step kernel's average duration, measured with
+HIP events on the solver's stream over a run of step kernels only.
+cpu_baseline: the FP64 NumPy oracle timed on the host for one time step of
+the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+BYTES_PER_POINT = {"f32": 16, "f16": 10, "bf16": 10}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("wave_kernels.hip", "wave_internal.h"):
+        with open(os.path.join(ROOT, "paper_2404_04441_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str):
+    """HBM bytes per step kernel from committed rocprofv3 counter runs, only
+    if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_step_large_{storage}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_sha") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(W, vel):
+    import numpy as np
+
+    import oracle
+
+    steps = 1
+    wav = W.wavelet(steps)
+    t0 = time.perf_counter()
+    oracle.forward(vel, W.h, W.dt, W.src, wav, W.rec, nt=steps, sponge_width=W.sponge_width,
+                   sponge_alpha=W.sponge_alpha)
+    t = time.perf_counter() - t0
+    return {"value": round(W.npts * steps / t / 1e9, 5), "unit": "Gpts/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} time step of the {W.name} workload (sponge, source, receivers), FP64 NumPy, "
+                      f"single thread, {t:.1f} s; host has {os.cpu_count()} CPUs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--nt", type=int, default=0, help="time steps per shot (default: the workload's 1000)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path (one shot per GPU).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2404_04441_amd import Solver
+    from synth import workload
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    W = workload("large")
+    nt = args.nt or W.nt
+    print(f"[bench] building {W.name} inputs", file=sys.stderr, flush=True)
+    vel = W.velocity()
+    wav = torch.from_numpy(W.wavelet(nt)).to(dev)
+    s = Solver(torch.from_numpy(vel).to(dev), W.h, W.dt, src=W.src, rec=W.rec, sponge_width=W.sponge_width,
+               sponge_alpha=W.sponge_alpha, storage=args.storage, variant=args.variant, zchunk=args.zchunk)
+    traces = torch.empty((nt, len(W.rec)), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        s.run(nt, wav, traces)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s.run(nt, wav, traces)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = W.npts * nt * args.steps / wall / 1e9
+    print(f"[bench] timed {args.steps} shots: {ms_per_step:.1f} ms/shot", file=sys.stderr, flush=True)
+
+    # step-kernel duration: events on the solver's own stream around step kernels only
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    s.reset()
+    e0.record(s.stream)
+    s.step(nt, wav, traces)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    kernel_ms = e0.elapsed_time(e1) / nt
+    bpp = BYTES_PER_POINT[args.storage]
+    achieved = bpp * W.npts / (kernel_ms * 1e-3) / 1e9
+    flags = s.sync_status()
+    s.close()
+
+    out = {
+        "metric": "stencil Gpts/s & % HBM roofline (1 GPU); shots/s with p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage == "f32" else f"{args.storage} storage, f32 arithmetic",
+        "data": "synthetic",
+        "config": {"workload": f"{W.name} FP32 fused forward shot: 8th-order star stencil, leapfrog, "
+                               f"20-node sponge, Ricker source at (256,256,10), 512x512 receiver plane z=0",
+                   "grid": list(W.shape[::-1]), "time_steps": nt, "storage": args.storage,
+                   "variant": args.variant, "zchunk": args.zchunk},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.storage),
+                     "kernel": "step_kernel", "kernel_ms": round(kernel_ms, 4),
+                     "algorithmic_bytes_per_launch": bpp * W.npts},
+        "nonfinite": bool(flags),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(W, vel)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,146 @@
+/*
+ * libwave -- 3D constant-density acoustic wave propagation on one gfx950 GPU.
+ *
+ * The operation (paper Sec. II, Eq. 1): the 25-point, 8th-order (radius 4)
+ * star Laplacian L, applied at every grid node once per time iteration to
+ * update the wavefield.  The time integrator (not named in the paper) is the
+ * 2nd-order leapfrog; an exponential sponge (Cerjan) damps the outer
+ * `sponge_width` nodes; a point source injects a wavelet; receivers sample
+ * the field.  One step, fused into one kernel pass over the grid:
+ *
+ *     A^{n+1} = g * (2 A^n - g * A^{n-1} + m * L(A^n) + q^n)
+ *     m       = (v dt)^2,   g = gx(x) gy(y) gz(z),
+ *     q^n     = dt^2 s(t_n) / (dx dy dz) at the source node, 0 elsewhere,
+ *     trace[n][r] = A^{n+1}(rec_r)
+ *
+ * L(u) = sum_a h_a^-2 [c0 u + sum_{m=1..4} c_m (u(+m e_a) + u(-m e_a))] with
+ * (c0..c4) = (-205/72, 8/5, -1/5, 8/315, -1/560); nodes outside the grid are
+ * zero.  This form is algebraically equal to damping both stored time levels
+ * each step; A^{n-1} is kept undamped in the buffer.
+ *
+ * Layout: every grid array is float32 (or the 16-bit storage type for the
+ * wavefields inside the workspace), x fastest: index = x + nx*(y + ny*z).
+ *
+ * Ownership: every device byte is allocated by the caller (velocity, the
+ * workspace, wavelet, traces, residual, gradient).  A context borrows its
+ * workspace, which must outlive it.  wave_destroy frees host memory only.
+ *
+ * Asynchrony: calls enqueue work on the context's HIP stream and return
+ * without waiting, except wave_create (reads back the velocity range) and
+ * wave_sync_status.  Argument errors are detected before anything is
+ * enqueued.  One host thread per context at a time; contexts on different
+ * streams run concurrently.
+ *
+ * Errors: every call returns WAVE_OK (0) or a negative status.  No call
+ * aborts, throws or prints.
+ */
+#ifndef LIBWAVE_WAVE_H
+#define LIBWAVE_WAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wave_ctx *wave_t;
+
+enum wave_status {
+  WAVE_OK = 0,
+  WAVE_EINVAL = -1,     /* bad argument: null pointer, size < 1, node outside the grid, bad enum */
+  WAVE_EUNSTABLE = -2,  /* dt exceeds the leapfrog stability limit for max(v) */
+  WAVE_ENOSPC = -3,     /* workspace smaller than wave_workspace_bytes() */
+  WAVE_EHIP = -4,       /* a HIP runtime call or kernel launch failed */
+  WAVE_ESTATE = -5      /* call not valid for this context (e.g. no adjoint workspace) */
+};
+
+enum wave_storage {
+  WAVE_F32 = 0,   /* float32 wavefields */
+  WAVE_F16 = 1,   /* IEEE half wavefields with a power-of-two scale per field, float32 arithmetic */
+  WAVE_BF16 = 2   /* bfloat16 wavefields, same scaling, float32 arithmetic */
+};
+
+/* Flags reported by wave_sync_status. */
+enum { WAVE_FLAG_NONFINITE = 1u };
+
+typedef struct {
+  int32_t nx, ny, nz;        /* grid nodes per axis, >= 1 */
+  double dx, dy, dz;         /* grid spacing (m), > 0 */
+  double dt;                 /* time step (s), > 0, at most the stability limit */
+  int32_t sponge_width;      /* damping strip width in nodes; 0 = zero-Dirichlet only */
+  double sponge_alpha;       /* strip factor: g = exp(-(alpha (W - d))^2) for distance d < W */
+  int32_t storage;           /* enum wave_storage */
+  int32_t src[3];            /* source node (ix, iy, iz); src[0] < 0: no source */
+  int32_t nrec;              /* number of receivers, >= 0 */
+  const int32_t *rec;        /* host array of 3*nrec node coordinates (ix, iy, iz), copied at create */
+  int32_t adjoint;           /* nonzero: reserve the workspace wave_adjoint needs (float32 only) */
+  int32_t nt_max;            /* adjoint: largest nt wave_adjoint will be called with */
+  int32_t ckpt_interval;     /* adjoint: steps between checkpoints; 0 = ceil(sqrt(nt_max)) */
+  int32_t variant;           /* kernel tiling variant (0 = default; see wave_variant_count) */
+  int32_t zchunk;            /* z-planes per workgroup; 0 = chosen from the grid size */
+  int32_t graph_steps;       /* >0: replay steps from a captured HIP graph of this many steps */
+} wave_params;
+
+/* Fill `p` with defaults: no source, no receivers, float32, alpha 0.015. */
+void wave_params_init(wave_params *p);
+
+/* Bytes of device workspace wave_create needs for `p` (256-byte aligned). */
+int wave_workspace_bytes(const wave_params *p, size_t *bytes);
+
+/* Create a context.  vel_dev: device float32 [nz][ny][nx] velocity (m/s),
+ * finite and > 0, read during the call only (m = (v dt)^2 is stored in the
+ * workspace).  ws_dev: device workspace of ws_bytes >= wave_workspace_bytes,
+ * 256-byte aligned.  hip_stream: the hipStream_t all work is queued on
+ * (NULL = default stream).  Synchronises that stream once.  The state is
+ * reset: A^0 = A^{-1} = 0, n = 0. */
+int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t ws_bytes,
+                void *hip_stream, wave_t *out);
+
+/* Zero both wavefields and the step counter n. */
+int wave_reset(wave_t w);
+
+/* Advance nsteps >= 0 steps from the current n.  wavelet_dev: device float32
+ * s(t_k) indexed by the absolute step k since the last reset (entries
+ * n..n+nsteps-1 are read; may be NULL without a source).  traces_dev: device
+ * float32 [k][nrec], absolute rows n..n+nsteps-1 are written (may be NULL
+ * when nrec == 0).  For 16-bit storage a trace holds the stored (rounded)
+ * value. */
+int wave_step(wave_t w, int32_t nsteps, const float *wavelet_dev, float *traces_dev);
+
+/* wave_reset followed by wave_step(nt). */
+int wave_run(wave_t w, int32_t nt, const float *wavelet_dev, float *traces_dev);
+
+/* Velocity gradient of J = 1/2 sum_{n,r} resid-weighted misfit: given the
+ * residual r^n = dJ/dtrace[n] (device float32 [nt][nrec]), writes
+ * grad_vel_dev (device float32, N) = dJ/dv, by the exact discrete adjoint of
+ * the step above with checkpointed recomputation of the forward field.
+ * Requires adjoint != 0 at create, storage == WAVE_F32 and nt <= nt_max.
+ * Leaves the context reset (n = 0). */
+int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *resid_dev,
+                 float *grad_vel_dev);
+
+/* Copy a wavefield, decoded to float32, into out_dev [nz][ny][nx]:
+ * which = 0: A^n, which = 1: A^{n-1} (undamped). */
+int wave_read_field(wave_t w, int32_t which, float *out_dev);
+
+/* Host copy of the step counter n. */
+int wave_time_index(wave_t w, int32_t *n);
+
+/* Synchronise the stream and report WAVE_FLAG_* bits for the current field. */
+int wave_sync_status(wave_t w, uint32_t *flags);
+
+/* Free the host context (the workspace stays the caller's). */
+int wave_destroy(wave_t w);
+
+/* Number of kernel tiling variants (valid values of wave_params.variant). */
+int wave_variant_count(void);
+
+/* Static text for a status code. */
+const char *wave_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBWAVE_WAVE_H */

@@ -20,6 +20,8 @@ What each module follows:
   time), with the sponge, point source and receivers.
 * ``adjoint`` -- exact discrete adjoint of ``forward`` and the velocity
   gradient of the L2 waveform misfit.
+* ``pointwise`` -- one step evaluated at chosen nodes (checks of grids too
+  large for the full loop).
 * ``energy``, ``analytic``, ``dense`` -- self-checks (discrete energy,
   constant-velocity Green's function, dense brute-force operator).
 * ``storage`` -- 16-bit wavefield storage with power-of-two scaling
@@ -33,9 +35,10 @@ from .energy import discrete_energy
 from .analytic import point_source_trace
 from .dense import dense_laplacian
 from .metrics import rel_l2, rel_max
+from .pointwise import step_at
 
 __all__ = [
     "fd_coefficients", "second_derivative_weights", "laplacian", "sponge_profile", "sponge_field",
     "stability_courant", "symbol_peak", "forward", "adjoint_fields", "gradient", "misfit",
-    "discrete_energy", "point_source_trace", "dense_laplacian", "rel_l2", "rel_max",
+    "discrete_energy", "point_source_trace", "dense_laplacian", "rel_l2", "rel_max", "step_at",
 ]

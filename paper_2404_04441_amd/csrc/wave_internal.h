@@ -1,0 +1,94 @@
+// Internal interface between the C-ABI runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace wave {
+
+constexpr int kRadius = 4;   // stencil half-width (8th order)
+constexpr int kTileX = 64;   // tile width in x: one wavefront row
+
+// Device-resident per-run state, at the head of the workspace.
+struct StepState {
+  int32_t n;            // absolute index of the next step (advanced by bump kernels)
+  int32_t pad0[3];
+  uint32_t amax[4];     // slot k%4: max |stored raw value| of field A^k (float bits)
+  int32_t exps[4];      // slot k%4: scale exponent e_k of field A^k (stored = A * 2^e)
+  uint32_t flags;       // WAVE_FLAG_* bits
+  uint32_t vmin_bits;   // velocity range from the create pass (float bits)
+  uint32_t vmax_bits;
+  uint32_t pad1[17];
+};
+static_assert(sizeof(StepState) == 128, "state block layout");
+
+struct Coef {
+  float k0;        // c0 * (1/dx^2 + 1/dy^2 + 1/dz^2)
+  float kx[4];     // c_m / dx^2
+  float ky[4];
+  float kz[4];
+};
+
+// Receivers forming a regular box, listed x fastest then y then z:
+// receiver (i, j, l) is node (x0 + i*sx, y0 + j*sy, z0 + l*sz), index
+// (l*cny + j)*cnx + i.  cnx == 0 means the fused path is off.
+struct RecBox {
+  int x0, sx, cnx;
+  int y0, sy, cny;
+  int z0, sz, cnz;
+};
+
+enum Storage { kF32 = 0, kF16 = 1, kBF16 = 2 };
+
+struct StepArgs {
+  const void *cur;    // A^n (storage type)
+  const void *prev;   // A^{n-1}
+  void *out;          // A^{n+1}; may alias prev
+  const float *m;     // (v dt)^2
+  const float *gx, *gy, *gz;
+  int nx, ny, nz;
+  int tiles_x, tiles_y, nchunks, zchunk, total_tiles;
+  Coef c;
+  int sx, sy, sz;     // source node; sx < 0: none
+  float src_scale;    // dt^2 / (dx dy dz)
+  const float *wavelet;
+  RecBox box;
+  float *traces;
+  int nrec;
+  StepState *st;
+  int k;              // this launch advances step st->n + k
+  float beta;         // 16-bit storage: growth bound of one step
+  // adjoint mode only
+  const float *fwd;   // forward field A^k for the imaging term
+  float *img;         // accumulator sum_k mu^{k+1} L(A^k)
+  const float *resid; // [nt][nrec] residual, injected at receivers
+  int resid_row;      // row of resid injected by this launch
+};
+
+struct Variant {
+  int by;   // wavefronts per workgroup (rows of 64 lanes)
+  int ry;   // rows per thread
+};
+
+int variant_count();
+Variant variant_info(int v);
+
+// Launchers; each returns the hipError_t of the launch.
+hipError_t launch_step(int storage, int variant, bool adjoint, const StepArgs &a, hipStream_t s);
+hipError_t launch_init_m(const float *vel, float *m, size_t n, float dt, StepState *st, hipStream_t s);
+hipError_t launch_bump(StepState *st, int count, hipStream_t s);
+hipError_t launch_decode(int storage, const void *field, float *out, size_t n, const StepState *st,
+                         int slot_from_n_offset, hipStream_t s);
+hipError_t launch_gather(int storage, const void *field, const int64_t *rec_lin, int nrec, float *traces,
+                         const StepState *st, int k, hipStream_t s);
+hipError_t launch_scatter(float *field, const int64_t *rec_lin, int nrec, const float *m, const float *grec,
+                          const float *resid, int row, hipStream_t s);
+hipError_t launch_reset_state(StepState *st, hipStream_t s);
+hipError_t launch_set_n(StepState *st, int n, hipStream_t s);
+hipError_t launch_check_finite(int storage, const void *field, size_t n, StepState *st, hipStream_t s);
+hipError_t launch_grad_final(const float *img, const float *m, float dt, float *grad, size_t n,
+                             hipStream_t s);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace wave

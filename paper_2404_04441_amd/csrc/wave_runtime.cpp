@@ -1,0 +1,553 @@
+// Host runtime of libwave: argument validation, workspace layout, FP64 host
+// tables (stencil weights, sponge profiles), receiver mapping, the time loop
+// with optional HIP-graph replay, and the checkpointed adjoint.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "wave.h"
+#include "wave_internal.h"
+
+using namespace wave;
+
+namespace {
+
+// Centred second-derivative weights, 8th order (Eq. 1 of paper Sec. II; the
+// paper leaves the values unprinted): the textbook values of Fornberg (1988).
+constexpr double kC[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+struct Layout {
+  size_t st, gx, gy, gz, rec_lin, grec, m, fa, fb, ckpt, seg, mua, mub, img, total;
+  int K, nck;
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int validate(const wave_params *p) {
+  if (!p) return WAVE_EINVAL;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return WAVE_EINVAL;
+  if (static_cast<int64_t>(p->nx) * p->ny >= (int64_t(1) << 31)) return WAVE_EINVAL;  // in-plane int offsets
+  if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dz) || !finite_pos(p->dt)) return WAVE_EINVAL;
+  if (p->sponge_width < 0 || !std::isfinite(p->sponge_alpha) || p->sponge_alpha < 0.0) return WAVE_EINVAL;
+  if (p->storage < WAVE_F32 || p->storage > WAVE_BF16) return WAVE_EINVAL;
+  if (p->src[0] >= 0) {
+    if (p->src[0] >= p->nx || p->src[1] < 0 || p->src[1] >= p->ny || p->src[2] < 0 || p->src[2] >= p->nz)
+      return WAVE_EINVAL;
+  }
+  if (p->nrec < 0 || (p->nrec > 0 && !p->rec)) return WAVE_EINVAL;
+  for (int r = 0; r < p->nrec; ++r) {
+    const int32_t *c = p->rec + 3 * r;
+    if (c[0] < 0 || c[0] >= p->nx || c[1] < 0 || c[1] >= p->ny || c[2] < 0 || c[2] >= p->nz) return WAVE_EINVAL;
+  }
+  if (p->adjoint) {
+    if (p->storage != WAVE_F32 || p->nt_max < 1 || p->ckpt_interval < 0) return WAVE_EINVAL;
+  }
+  if (p->variant < 0 || p->variant >= variant_count()) return WAVE_EINVAL;
+  if (p->zchunk < 0 || p->graph_steps < 0) return WAVE_EINVAL;
+  return WAVE_OK;
+}
+
+int plan(const wave_params *p, Layout *L) {
+  const int rc = validate(p);
+  if (rc) return rc;
+  const size_t N = static_cast<size_t>(p->nx) * p->ny * p->nz;
+  const size_t es = p->storage == WAVE_F32 ? 4 : 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  L->st = take(sizeof(StepState));
+  L->gx = take(4 * static_cast<size_t>(p->nx));
+  L->gy = take(4 * static_cast<size_t>(p->ny));
+  L->gz = take(4 * static_cast<size_t>(p->nz));
+  L->rec_lin = take(8 * static_cast<size_t>(p->nrec));
+  L->grec = take(4 * static_cast<size_t>(p->nrec));
+  L->m = take(4 * N);
+  L->fa = take(es * N);
+  L->fb = take(es * N);
+  L->K = 0;
+  L->nck = 0;
+  L->ckpt = L->seg = L->mua = L->mub = L->img = off;
+  if (p->adjoint) {
+    int K = p->ckpt_interval;
+    if (K <= 0) K = static_cast<int>(std::ceil(std::sqrt(static_cast<double>(p->nt_max))));
+    K = std::max(1, std::min(K, p->nt_max));
+    const int nseg = (p->nt_max + K - 1) / K;
+    L->K = K;
+    L->nck = nseg - 1;
+    L->ckpt = take(4 * N * 2 * static_cast<size_t>(L->nck));
+    L->seg = take(4 * N * static_cast<size_t>(K + 2));
+    L->mua = take(4 * N);
+    L->mub = take(4 * N);
+    L->img = take(4 * N);
+  }
+  L->total = off;
+  return WAVE_OK;
+}
+
+std::vector<float> sponge_table(int n, int width, double alpha) {
+  std::vector<float> g(n);
+  for (int i = 0; i < n; ++i) {
+    const int d = std::min(i, n - 1 - i);
+    const double t = d < width ? alpha * (width - d) : 0.0;
+    g[i] = static_cast<float>(d < width ? std::exp(-t * t) : 1.0);
+  }
+  return g;
+}
+
+// If the receivers are a regular box listed x fastest, then y, then z, fill
+// `b` and return true.
+bool detect_box(const std::vector<int32_t> &rec, int nrec, RecBox *b) {
+  if (nrec == 0) return false;
+  auto X = [&](int r) { return rec[3 * r]; };
+  auto Y = [&](int r) { return rec[3 * r + 1]; };
+  auto Z = [&](int r) { return rec[3 * r + 2]; };
+  int cnx = 1;
+  while (cnx < nrec && Y(cnx) == Y(0) && Z(cnx) == Z(0)) ++cnx;
+  const int sx = cnx > 1 ? X(1) - X(0) : 1;
+  if (sx <= 0 || nrec % cnx) return false;
+  int cny = 1;
+  while (cny * cnx < nrec && Z(cny * cnx) == Z(0)) ++cny;
+  const int sy = cny > 1 ? Y(cnx) - Y(0) : 1;
+  if (sy <= 0 || nrec % (cnx * cny)) return false;
+  const int cnz = nrec / (cnx * cny);
+  const int sz = cnz > 1 ? Z(cnx * cny) - Z(0) : 1;
+  if (sz <= 0) return false;
+  for (int l = 0; l < cnz; ++l)
+    for (int j = 0; j < cny; ++j)
+      for (int i = 0; i < cnx; ++i) {
+        const int r = (l * cny + j) * cnx + i;
+        if (X(r) != X(0) + i * sx || Y(r) != Y(0) + j * sy || Z(r) != Z(0) + l * sz) return false;
+      }
+  *b = RecBox{X(0), sx, cnx, Y(0), sy, cny, Z(0), sz, cnz};
+  return true;
+}
+
+}  // namespace
+
+struct wave_ctx {
+  wave_params p{};
+  std::vector<int32_t> rec;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  Layout L{};
+  StepState *st = nullptr;
+  float *gx = nullptr, *gy = nullptr, *gz = nullptr, *m = nullptr, *grec = nullptr;
+  int64_t *rec_lin = nullptr;
+  void *fa = nullptr, *fb = nullptr;
+  size_t N = 0;
+  int n = 0;  // host mirror of the step counter
+  Coef c{};
+  float src_scale = 0.f, beta = 2.f;
+  RecBox box{};
+  bool fused_rec = false;
+  int tiles_x = 0, tiles_y = 0, nchunks = 0, zchunk = 0, total_tiles = 0;
+  // graph replay cache: one graph per buffer parity
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  const float *g_wavelet = nullptr;
+  float *g_traces = nullptr;
+
+  ~wave_ctx() { drop_graphs(); }
+  void drop_graphs() {
+    for (auto &g : graph)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  }
+  void *field(int parity) const { return parity ? fb : fa; }  // A^k lives in field(k & 1)
+};
+
+namespace {
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? WAVE_OK : WAVE_EHIP; }
+
+StepArgs base_args(const wave_ctx *w) {
+  StepArgs a{};
+  a.m = w->m;
+  a.gx = w->gx;
+  a.gy = w->gy;
+  a.gz = w->gz;
+  a.nx = w->p.nx;
+  a.ny = w->p.ny;
+  a.nz = w->p.nz;
+  a.tiles_x = w->tiles_x;
+  a.tiles_y = w->tiles_y;
+  a.nchunks = w->nchunks;
+  a.zchunk = w->zchunk;
+  a.total_tiles = w->total_tiles;
+  a.c = w->c;
+  a.sx = w->p.src[0] >= 0 ? w->p.src[0] : -1;
+  a.sy = w->p.src[1];
+  a.sz = w->p.src[2];
+  a.src_scale = w->src_scale;
+  a.st = w->st;
+  a.beta = w->beta;
+  a.nrec = w->p.nrec;
+  return a;
+}
+
+// Enqueue `count` forward steps starting at device counter st->n (and host
+// n), then advance the counter.  sample = write traces.
+int enqueue_steps(wave_ctx *w, int count, const float *wavelet, float *traces, bool sample) {
+  StepArgs a = base_args(w);
+  a.wavelet = wavelet;
+  a.traces = traces;
+  if (sample && w->fused_rec) a.box = w->box;
+  for (int k = 0; k < count; ++k) {
+    const int parity = (w->n + k) & 1;
+    a.cur = w->field(parity);
+    a.prev = w->field(parity ^ 1);
+    a.out = w->field(parity ^ 1);
+    a.k = k;
+    int rc = hip_rc(launch_step(w->p.storage, w->p.variant, false, a, w->stream));
+    if (rc) return rc;
+    if (sample && !w->fused_rec && w->p.nrec > 0) {
+      rc = hip_rc(launch_gather(w->p.storage, a.out, w->rec_lin, w->p.nrec, traces, w->st, k, w->stream));
+      if (rc) return rc;
+    }
+  }
+  return hip_rc(launch_bump(w->st, count, w->stream));
+}
+
+// Replay `reps` times a captured graph of graph_steps steps (even count, so
+// the buffer parity is the same at every replay).
+int replay_graph(wave_ctx *w, int reps, const float *wavelet, float *traces) {
+  const int K = w->p.graph_steps;
+  if (w->g_wavelet != wavelet || w->g_traces != traces) {
+    w->drop_graphs();
+    w->g_wavelet = wavelet;
+    w->g_traces = traces;
+  }
+  const int parity = w->n & 1;
+  if (!w->graph[parity]) {
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return WAVE_EHIP;
+    hipGraph_t g = nullptr;
+    int rc = hip_rc(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    if (!rc) {
+      hipStream_t saved = w->stream;
+      const int saved_n = w->n;
+      w->stream = cs;
+      rc = enqueue_steps(w, K, wavelet, traces, true);
+      w->stream = saved;
+      w->n = saved_n;
+      const int rc2 = hip_rc(hipStreamEndCapture(cs, &g));
+      if (!rc) rc = rc2;
+    }
+    if (!rc) rc = hip_rc(hipGraphInstantiate(&w->graph[parity], g, nullptr, nullptr, 0));
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (rc) return rc;
+  }
+  for (int r = 0; r < reps; ++r) {
+    const int rc = hip_rc(hipGraphLaunch(w->graph[parity], w->stream));
+    if (rc) return rc;
+  }
+  w->n += reps * K;
+  return WAVE_OK;
+}
+
+int do_step(wave_ctx *w, int nsteps, const float *wavelet, float *traces) {
+  int done = 0;
+  const int K = w->p.graph_steps;
+  if (K > 0 && K % 2 == 0 && nsteps >= K) {
+    const int reps = nsteps / K;
+    const int rc = replay_graph(w, reps, wavelet, traces);
+    if (rc) return rc;
+    done = reps * K;
+  }
+  if (nsteps - done > 0) {
+    const int rc = enqueue_steps(w, nsteps - done, wavelet, traces, true);
+    if (rc) return rc;
+    w->n += nsteps - done;
+  }
+  return WAVE_OK;
+}
+
+int do_reset(wave_ctx *w) {
+  const size_t es = w->p.storage == WAVE_F32 ? 4 : 2;
+  int rc = hip_rc(launch_fill_zero(w->fa, es * w->N, w->stream));
+  if (!rc) rc = hip_rc(launch_fill_zero(w->fb, es * w->N, w->stream));
+  if (!rc) rc = hip_rc(launch_reset_state(w->st, w->stream));
+  if (!rc) w->n = 0;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void wave_params_init(wave_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->dx = p->dy = p->dz = 1.0;
+  p->dt = 1.0;
+  p->sponge_alpha = 0.015;
+  p->storage = WAVE_F32;
+  p->src[0] = -1;
+}
+
+int wave_workspace_bytes(const wave_params *p, size_t *bytes) {
+  if (!bytes) return WAVE_EINVAL;
+  Layout L;
+  const int rc = plan(p, &L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return WAVE_OK;
+}
+
+int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t ws_bytes, void *hip_stream,
+                wave_t *out) {
+  if (!out || !vel_dev || !ws_dev) return WAVE_EINVAL;
+  *out = nullptr;
+  Layout L;
+  int rc = plan(p, &L);
+  if (rc) return rc;
+  if (reinterpret_cast<uintptr_t>(ws_dev) % 256) return WAVE_EINVAL;
+  if (ws_bytes < L.total) return WAVE_ENOSPC;
+
+  wave_ctx *w = new (std::nothrow) wave_ctx();
+  if (!w) return WAVE_EINVAL;
+  w->p = *p;
+  w->rec.assign(p->rec, p->rec + 3 * static_cast<size_t>(p->nrec));
+  w->p.rec = nullptr;  // never keep the caller's pointer
+  w->stream = static_cast<hipStream_t>(hip_stream);
+  w->ws = static_cast<char *>(ws_dev);
+  w->L = L;
+  w->st = reinterpret_cast<StepState *>(w->ws + L.st);
+  w->gx = reinterpret_cast<float *>(w->ws + L.gx);
+  w->gy = reinterpret_cast<float *>(w->ws + L.gy);
+  w->gz = reinterpret_cast<float *>(w->ws + L.gz);
+  w->rec_lin = reinterpret_cast<int64_t *>(w->ws + L.rec_lin);
+  w->grec = reinterpret_cast<float *>(w->ws + L.grec);
+  w->m = reinterpret_cast<float *>(w->ws + L.m);
+  w->fa = w->ws + L.fa;
+  w->fb = w->ws + L.fb;
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  w->N = static_cast<size_t>(nx) * ny * nz;
+
+  // FP64 host tables
+  const double ix2 = 1.0 / (p->dx * p->dx), iy2 = 1.0 / (p->dy * p->dy), iz2 = 1.0 / (p->dz * p->dz);
+  w->c.k0 = static_cast<float>(kC[0] * (ix2 + iy2 + iz2));
+  for (int m = 1; m <= 4; ++m) {
+    w->c.kx[m - 1] = static_cast<float>(kC[m] * ix2);
+    w->c.ky[m - 1] = static_cast<float>(kC[m] * iy2);
+    w->c.kz[m - 1] = static_cast<float>(kC[m] * iz2);
+  }
+  w->src_scale = static_cast<float>(p->dt * p->dt / (p->dx * p->dy * p->dz));
+  const std::vector<float> gx = sponge_table(nx, p->sponge_width, p->sponge_alpha);
+  const std::vector<float> gy = sponge_table(ny, p->sponge_width, p->sponge_alpha);
+  const std::vector<float> gz = sponge_table(nz, p->sponge_width, p->sponge_alpha);
+  std::vector<int64_t> lin(p->nrec);
+  std::vector<float> grec(p->nrec);
+  for (int r = 0; r < p->nrec; ++r) {
+    const int x = w->rec[3 * r], y = w->rec[3 * r + 1], z = w->rec[3 * r + 2];
+    lin[r] = x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z);
+    grec[r] = static_cast<float>(static_cast<double>(gx[x]) * gy[y] * gz[z]);
+  }
+  w->fused_rec = detect_box(w->rec, p->nrec, &w->box);
+  if (!w->fused_rec) w->box = RecBox{};
+
+  // tiling
+  const Variant v = variant_info(p->variant);
+  const int TY = v.by * v.ry;
+  w->tiles_x = (nx + kTileX - 1) / kTileX;
+  w->tiles_y = (ny + TY - 1) / TY;
+  int zc = p->zchunk;
+  if (zc <= 0) {
+    const int per_plane = w->tiles_x * w->tiles_y;
+    const int want = 2048;  // >= 8 workgroups per CU in flight
+    const int chunks = std::max(1, (want + per_plane - 1) / per_plane);
+    zc = std::max(16, (nz + chunks - 1) / chunks);
+  }
+  w->zchunk = std::min(zc, nz);
+  w->nchunks = (nz + w->zchunk - 1) / w->zchunk;
+  w->total_tiles = w->tiles_x * w->tiles_y * w->nchunks;
+
+  StepState init{};
+  init.vmin_bits = 0x7f800000u;
+  init.vmax_bits = 0u;
+  StepState back{};
+  rc = hip_rc(hipMemcpyAsync(w->st, &init, sizeof(init), hipMemcpyHostToDevice, w->stream));
+  if (!rc) rc = hip_rc(hipMemcpyAsync(w->gx, gx.data(), 4 * gx.size(), hipMemcpyHostToDevice, w->stream));
+  if (!rc) rc = hip_rc(hipMemcpyAsync(w->gy, gy.data(), 4 * gy.size(), hipMemcpyHostToDevice, w->stream));
+  if (!rc) rc = hip_rc(hipMemcpyAsync(w->gz, gz.data(), 4 * gz.size(), hipMemcpyHostToDevice, w->stream));
+  if (!rc && p->nrec > 0) {
+    rc = hip_rc(hipMemcpyAsync(w->rec_lin, lin.data(), 8 * lin.size(), hipMemcpyHostToDevice, w->stream));
+    if (!rc) rc = hip_rc(hipMemcpyAsync(w->grec, grec.data(), 4 * grec.size(), hipMemcpyHostToDevice, w->stream));
+  }
+  if (!rc) rc = hip_rc(launch_init_m(vel_dev, w->m, w->N, static_cast<float>(p->dt), w->st, w->stream));
+  if (!rc) rc = hip_rc(hipMemcpyAsync(&back, w->st, sizeof(back), hipMemcpyDeviceToHost, w->stream));
+  if (!rc) rc = hip_rc(hipStreamSynchronize(w->stream));
+  if (!rc && (back.flags & 2u)) rc = WAVE_EINVAL;  // non-finite or non-positive velocity
+  if (!rc) {
+    float vmax;
+    std::memcpy(&vmax, &back.vmax_bits, 4);
+    const double peak = 2048.0 / 315.0;  // max |symbol| of the 1D stencil, at the Nyquist wavenumber
+    const double Mmax = static_cast<double>(vmax) * p->dt * static_cast<double>(vmax) * p->dt;
+    if (Mmax * peak * (ix2 + iy2 + iz2) > 4.0 * (1.0 + 1e-12)) rc = WAVE_EUNSTABLE;
+    // growth bound of one step for the 16-bit scale:
+    // |2A + M L A| <= (|2 + M k0| + M sum |k|) max|A|
+    double kabs = 0.0;
+    for (int m = 1; m <= 4; ++m) kabs += 2.0 * std::fabs(kC[m]) * (ix2 + iy2 + iz2);
+    const double k0 = kC[0] * (ix2 + iy2 + iz2);
+    w->beta = static_cast<float>(std::max(2.0, std::fabs(2.0 + Mmax * k0) + Mmax * kabs) * (1.0 + 1e-6));
+  }
+  if (!rc) rc = do_reset(w);
+  if (rc) {
+    delete w;
+    return rc;
+  }
+  *out = w;
+  return WAVE_OK;
+}
+
+int wave_reset(wave_t w) {
+  if (!w) return WAVE_EINVAL;
+  return do_reset(w);
+}
+
+int wave_step(wave_t w, int32_t nsteps, const float *wavelet_dev, float *traces_dev) {
+  if (!w || nsteps < 0) return WAVE_EINVAL;
+  if (nsteps == 0) return WAVE_OK;
+  if (w->p.src[0] >= 0 && !wavelet_dev) return WAVE_EINVAL;
+  if (w->p.nrec > 0 && !traces_dev) return WAVE_EINVAL;
+  return do_step(w, nsteps, wavelet_dev, traces_dev);
+}
+
+int wave_run(wave_t w, int32_t nt, const float *wavelet_dev, float *traces_dev) {
+  if (!w || nt < 0) return WAVE_EINVAL;
+  if (nt > 0 && w->p.src[0] >= 0 && !wavelet_dev) return WAVE_EINVAL;
+  if (nt > 0 && w->p.nrec > 0 && !traces_dev) return WAVE_EINVAL;
+  const int rc = do_reset(w);
+  if (rc) return rc;
+  return nt > 0 ? do_step(w, nt, wavelet_dev, traces_dev) : WAVE_OK;
+}
+
+int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *resid_dev, float *grad_vel_dev) {
+  if (!w) return WAVE_EINVAL;
+  if (!w->p.adjoint) return WAVE_ESTATE;
+  if (nt < 1 || nt > w->p.nt_max || !grad_vel_dev) return WAVE_EINVAL;
+  if (w->p.src[0] >= 0 && !wavelet_dev) return WAVE_EINVAL;
+  if (w->p.nrec > 0 && !resid_dev) return WAVE_EINVAL;
+  const Layout &L = w->L;
+  const int K = L.K;
+  const size_t fb = 4 * w->N;  // bytes per float32 field
+  float *ckpt = reinterpret_cast<float *>(w->ws + L.ckpt);
+  float *seg = reinterpret_cast<float *>(w->ws + L.seg);
+  float *mu1 = reinterpret_cast<float *>(w->ws + L.mua);  // mu^{k+1}
+  float *mu2 = reinterpret_cast<float *>(w->ws + L.mub);  // mu^{k+2}
+  float *img = reinterpret_cast<float *>(w->ws + L.img);
+  auto slot = [&](int s) { return seg + static_cast<size_t>(s) * w->N; };
+  const int nseg = (nt + K - 1) / K;
+  w->drop_graphs();
+
+  // 1) forward run storing (A^{jK}, A^{jK-1}) for j = 1..nseg-1
+  int rc = do_reset(w);
+  for (int j = 1; j < nseg && !rc; ++j) {
+    rc = enqueue_steps(w, K, wavelet_dev, nullptr, false);
+    if (rc) break;
+    w->n += K;
+    float *ck = ckpt + 2 * static_cast<size_t>(j - 1) * w->N;
+    rc = hip_rc(hipMemcpyAsync(ck, w->field(w->n & 1), fb, hipMemcpyDeviceToDevice, w->stream));
+    if (!rc) rc = hip_rc(hipMemcpyAsync(ck + w->N, w->field((w->n & 1) ^ 1), fb, hipMemcpyDeviceToDevice, w->stream));
+  }
+  if (!rc) rc = hip_rc(launch_fill_zero(mu1, fb, w->stream));
+  if (!rc) rc = hip_rc(launch_fill_zero(mu2, fb, w->stream));
+  if (!rc) rc = hip_rc(launch_fill_zero(img, fb, w->stream));
+
+  // 2) segments from last to first: recompute A^{jK+1..}, then adjoint steps
+  for (int j = nseg - 1; j >= 0 && !rc; --j) {
+    const int k_lo = j * K + 1, k_hi = std::min((j + 1) * K, nt);
+    if (j == 0) {
+      rc = hip_rc(launch_fill_zero(slot(0), 2 * fb, w->stream));
+    } else {
+      const float *ck = ckpt + 2 * static_cast<size_t>(j - 1) * w->N;
+      rc = hip_rc(hipMemcpyAsync(slot(1), ck, fb, hipMemcpyDeviceToDevice, w->stream));
+      if (!rc) rc = hip_rc(hipMemcpyAsync(slot(0), ck + w->N, fb, hipMemcpyDeviceToDevice, w->stream));
+    }
+    if (!rc) rc = hip_rc(launch_set_n(w->st, j * K, w->stream));
+    // slot s holds A^{jK - 1 + s}
+    StepArgs a = base_args(w);
+    a.wavelet = wavelet_dev;
+    for (int k = 0; k < k_hi - j * K && !rc; ++k) {
+      a.cur = slot(k + 1);
+      a.prev = slot(k);
+      a.out = slot(k + 2);
+      a.k = k;
+      rc = hip_rc(launch_step(WAVE_F32, w->p.variant, false, a, w->stream));
+    }
+    StepArgs b = base_args(w);
+    b.sx = -1;
+    b.img = img;
+    b.resid = resid_dev;
+    if (w->fused_rec) b.box = w->box;
+    for (int k = k_hi; k >= k_lo && !rc; --k) {
+      b.cur = mu1;
+      b.prev = mu2;
+      b.out = mu2;  // mu^k overwrites mu^{k+2}
+      b.fwd = slot(k - j * K + 1);
+      b.resid_row = k - 1;
+      rc = hip_rc(launch_step(WAVE_F32, w->p.variant, true, b, w->stream));
+      if (!rc && !w->fused_rec && w->p.nrec > 0)
+        rc = hip_rc(launch_scatter(mu2, w->rec_lin, w->p.nrec, w->m, w->grec, resid_dev, k - 1, w->stream));
+      std::swap(mu1, mu2);
+    }
+  }
+  if (!rc) rc = hip_rc(launch_grad_final(img, w->m, static_cast<float>(w->p.dt), grad_vel_dev, w->N, w->stream));
+  if (!rc) rc = do_reset(w);
+  return rc;
+}
+
+int wave_read_field(wave_t w, int32_t which, float *out_dev) {
+  if (!w || !out_dev || (which != 0 && which != 1)) return WAVE_EINVAL;
+  const void *f = w->field((w->n & 1) ^ which);
+  return hip_rc(launch_decode(w->p.storage, f, out_dev, w->N, w->st, which ? 3 : 0, w->stream));
+}
+
+int wave_time_index(wave_t w, int32_t *n) {
+  if (!w || !n) return WAVE_EINVAL;
+  *n = w->n;
+  return WAVE_OK;
+}
+
+int wave_sync_status(wave_t w, uint32_t *flags) {
+  if (!w || !flags) return WAVE_EINVAL;
+  int rc = hip_rc(launch_check_finite(w->p.storage, w->field(w->n & 1), w->N, w->st, w->stream));
+  StepState back{};
+  if (!rc) rc = hip_rc(hipMemcpyAsync(&back, w->st, sizeof(back), hipMemcpyDeviceToHost, w->stream));
+  if (!rc) rc = hip_rc(hipStreamSynchronize(w->stream));
+  if (!rc) *flags = back.flags & WAVE_FLAG_NONFINITE;
+  return rc;
+}
+
+int wave_destroy(wave_t w) {
+  if (!w) return WAVE_EINVAL;
+  delete w;
+  return WAVE_OK;
+}
+
+int wave_variant_count(void) { return variant_count(); }
+
+const char *wave_status_string(int status) {
+  switch (status) {
+    case WAVE_OK: return "ok";
+    case WAVE_EINVAL: return "invalid argument";
+    case WAVE_EUNSTABLE: return "time step above the stability limit";
+    case WAVE_ENOSPC: return "workspace too small";
+    case WAVE_EHIP: return "HIP runtime error";
+    case WAVE_ESTATE: return "call not valid for this context";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

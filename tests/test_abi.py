@@ -1,0 +1,138 @@
+"""The C ABI on the host: symbols, struct layout and argument validation.
+
+No test here launches GPU work; every call below returns before the first
+HIP call (validation happens first by contract).
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2404_04441_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wave.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2404_04441_amd.build import build
+        build()
+    return L.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wave_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_params_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "layout.c"
+    fields = [f for f, _ in L.WaveParams._fields_]
+    body = "\n".join(f'printf("{f} %zu\\n", offsetof(wave_params, {f}));' for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "wave.h"\n'
+                   'int main(void){' + body + 'printf("size %zu\\n", sizeof(wave_params));return 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines())
+    for f in fields:
+        assert int(out[f]) == getattr(L.WaveParams, f).offset, f
+    assert int(out["size"]) == ctypes.sizeof(L.WaveParams)
+
+
+def _params(lib, **kw):
+    p = L.WaveParams()
+    lib.wave_params_init(ctypes.byref(p))
+    p.nx, p.ny, p.nz = 16, 12, 10
+    p.dx = p.dy = p.dz = 10.0
+    p.dt = 1e-4
+    for k, v in kw.items():
+        if k == "src":
+            p.src[0], p.src[1], p.src[2] = v
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _bytes(lib, p):
+    b = ctypes.c_size_t()
+    rc = lib.wave_workspace_bytes(ctypes.byref(p), ctypes.byref(b))
+    return rc, b.value
+
+
+def test_workspace_bytes(lib):
+    rc, b32 = _bytes(lib, _params(lib))
+    assert rc == 0 and b32 % 256 == 0
+    N = 16 * 12 * 10
+    assert b32 >= 3 * 4 * N  # m and two float32 fields
+    rc, b16 = _bytes(lib, _params(lib, storage=L.WAVE_F16))
+    assert rc == 0 and b16 < b32
+    rc, badj = _bytes(lib, _params(lib, adjoint=1, nt_max=100))
+    # 10 steps per checkpoint: 9 checkpoint pairs + 12 segment slots + 3 adjoint fields
+    assert rc == 0 and badj - b32 >= 4 * N * (2 * 9 + 12 + 3)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(nx=0), dict(nz=-1), dict(dt=0.0), dict(dx=float("nan")), dict(storage=3),
+    dict(src=(16, 0, 0)), dict(src=(0, -1, 0)), dict(sponge_width=-1), dict(sponge_alpha=-0.1),
+    dict(adjoint=1, nt_max=0), dict(adjoint=1, nt_max=10, storage=L.WAVE_F16), dict(variant=99),
+    dict(zchunk=-2), dict(graph_steps=-1),
+])
+def test_invalid_params_rejected(lib, kw):
+    rc, _ = _bytes(lib, _params(lib, **kw))
+    assert rc == L.WAVE_EINVAL
+
+
+def test_receivers_validated(lib):
+    rec = (ctypes.c_int32 * 6)(1, 2, 3, 16, 0, 0)  # second receiver outside in x
+    p = _params(lib, nrec=2)
+    p.rec = ctypes.cast(rec, ctypes.POINTER(ctypes.c_int32))
+    assert _bytes(lib, p)[0] == L.WAVE_EINVAL
+    p = _params(lib, nrec=2)  # null pointer with nrec > 0
+    assert _bytes(lib, p)[0] == L.WAVE_EINVAL
+
+
+def test_create_checks_before_any_gpu_call(lib):
+    p = _params(lib)
+    rc, need = _bytes(lib, p)
+    h = ctypes.c_void_p()
+    fake = 1 << 20  # never dereferenced: every call below fails validation first
+    assert lib.wave_create(ctypes.byref(p), fake, fake, need - 256, None, ctypes.byref(h)) == L.WAVE_ENOSPC
+    assert lib.wave_create(ctypes.byref(p), fake, fake + 8, need, None, ctypes.byref(h)) == L.WAVE_EINVAL
+    assert lib.wave_create(ctypes.byref(p), None, fake, need, None, ctypes.byref(h)) == L.WAVE_EINVAL
+    assert lib.wave_create(ctypes.byref(p), fake, fake, need, None, None) == L.WAVE_EINVAL
+    bad = _params(lib, nx=0)
+    assert lib.wave_create(ctypes.byref(bad), fake, fake, need, None, ctypes.byref(h)) == L.WAVE_EINVAL
+
+
+def test_null_context_calls(lib):
+    n = ctypes.c_int32()
+    f = ctypes.c_uint32()
+    assert lib.wave_step(None, 1, None, None) == L.WAVE_EINVAL
+    assert lib.wave_run(None, 1, None, None) == L.WAVE_EINVAL
+    assert lib.wave_reset(None) == L.WAVE_EINVAL
+    assert lib.wave_adjoint(None, 1, None, None, None) == L.WAVE_EINVAL
+    assert lib.wave_read_field(None, 0, None) == L.WAVE_EINVAL
+    assert lib.wave_time_index(None, ctypes.byref(n)) == L.WAVE_EINVAL
+    assert lib.wave_sync_status(None, ctypes.byref(f)) == L.WAVE_EINVAL
+    assert lib.wave_destroy(None) == L.WAVE_EINVAL
+    assert lib.wave_workspace_bytes(None, None) == L.WAVE_EINVAL
+
+
+def test_status_strings_and_variants(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.status_string(code)
+    assert L.status_string(-77) == "unknown status"
+    assert lib.wave_variant_count() >= 1

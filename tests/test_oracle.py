@@ -360,3 +360,23 @@ def test_paper_traffic_is_16_bytes_per_point():
     vals = dict(l.split() for l in _read_fracs("paper_traffic.txt"))
     bpp = float(vals["bytes_per_step"]) / float(vals["grid_points"])
     assert abs(bpp - 16.0) < 0.1  # three float32 reads + one float32 write
+
+
+def test_pointwise_step_equals_full_loop():
+    """step_at (25 explicit taps per node) reproduces one step of the full
+    loop at every node of a small grid, sponge and source included."""
+    shape, h = (12, 11, 13), 10.0
+    vel = smooth_random(shape, seed=31).astype(np.float64)
+    dt = COURANT * h / vel.max()
+    W, alpha = 3, 0.1
+    rng = np.random.default_rng(31)
+    w = rng.standard_normal(6)
+    src = (6, 5, 4)
+    fw = oracle.forward(vel, h, dt, src, w[:5], np.zeros((0, 3), int), nt=5, sponge_width=W,
+                        sponge_alpha=alpha, history=True)
+    A_n, A_nm1 = fw["history"][5], fw["history"][4]
+    nxt = oracle.forward(vel, h, dt, src, w, np.zeros((0, 3), int), nt=6, sponge_width=W, sponge_alpha=alpha)["u"]
+    zz, yy, xx = np.meshgrid(*(np.arange(n) for n in shape), indexing="ij")
+    pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+    got = oracle.step_at(pts, A_n, A_nm1, vel, h, dt, src=src, s_n=w[5], sponge_width=W, sponge_alpha=alpha)
+    assert np.abs(got - nxt.ravel()).max() <= 1e-13 * np.abs(nxt).max()

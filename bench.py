@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--nt", type=int, default=0, help="time steps per shot (default: the workload's 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 2 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path (one shot per GPU).",
@@ -130,6 +132,17 @@ def main():
     achieved = bpp * W.npts / (kernel_ms * 1e-3) / 1e9
     flags = s.sync_status()
     s.close()
+
+    if args.copy_calibration:
+        # a plain copy of known size: its FETCH_SIZE/WRITE_SIZE counters give
+        # the factor between counter readings and bytes moved
+        src = torch.ones(1 << 29, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 x {src.numel() * 4} bytes read and written", file=sys.stderr,
+              flush=True)
 
     out = {
         "metric": "stencil Gpts/s & % HBM roofline (1 GPU); shots/s with p50/p99 latency",

@@ -67,8 +67,9 @@ struct StepArgs {
 };
 
 struct Variant {
-  int by;   // wavefronts per workgroup (rows of 64 lanes)
-  int ry;   // rows per thread
+  int by;   // wavefronts per workgroup
+  int ry;   // consecutive rows per wavefront (tile height = by * ry)
+  int pd;   // z-planes of loads in flight ahead of the plane being computed
 };
 
 int variant_count();

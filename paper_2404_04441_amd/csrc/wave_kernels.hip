@@ -6,14 +6,16 @@
 // paper Sec. IV-A (tile x and y, stream along z) redesigned for CDNA4:
 //
 //  * a workgroup owns a 64 x TY column of the grid (TY = BY*RY rows) over a
-//    z-chunk; each 64-lane wavefront covers one 256-byte row segment, so every
-//    global access of the interior is a fully coalesced row;
+//    z-chunk; each 64-lane wavefront owns RY consecutive rows, so every global
+//    access of the interior is a fully coalesced 256-byte row whose address
+//    is wavefront-uniform (scalar row base + one shared lane offset);
 //  * the centre xy plane (with its radius-4 x/y halo) is staged in LDS, double
-//    buffered so one barrier per plane suffices;
+//    buffered so one barrier per plane suffices; y neighbours inside a
+//    wavefront's own rows come from registers instead;
 //  * the 9 values each thread needs along z live in a register queue that
 //    shifts by one plane per iteration; A^n is read from HBM once per chunk;
-//  * loads for plane z+1 are issued before the barrier of plane z, so their
-//    latency overlaps the stencil arithmetic of plane z;
+//  * loads run PD planes ahead of the plane being computed (a register
+//    pipeline), so enough bytes are in flight to cover HBM latency;
 //  * A^{n-1}, m and A^{n+1} are touched exactly once: they use nontemporal
 //    loads/stores so that L2 keeps the A^n planes the neighbours' halos need;
 //  * workgroup ids are remapped so that each XCD (hardware dispatches ids
@@ -72,18 +74,83 @@ template <> struct Codec<kBF16> {
 template <typename T> __device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
 template <typename T> __device__ __forceinline__ void st_stream(T v, T *p) { __builtin_nontemporal_store(v, p); }
 
-template <int S, int BY, int RY, bool ADJ>
+// ---- buffer access: a per-plane resource (scalar base), a scalar byte offset
+// for the row and one 32-bit lane offset; every address used is inside the
+// array (rows, planes and columns are clamped), ghost values are selected
+// to zero where they are consumed.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
+constexpr int kNT = 2;                  // nontemporal cache policy bit
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), static_cast<short>(0),
+                                           static_cast<int>(bytes), kRsrcWord3);
+}
+
+template <typename T> struct Buf;
+template <> struct Buf<float> {
+  template <int AUX> __device__ static float ld(rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(vo),
+                                                                          static_cast<int>(so), AUX));
+  }
+  template <int AUX> __device__ static void st(float v, rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, static_cast<int>(vo),
+                                          static_cast<int>(so), AUX);
+  }
+};
+template <> struct Buf<uint16_t> {
+  template <int AUX> __device__ static uint16_t ld(rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(vo), static_cast<int>(so), AUX);
+  }
+  template <int AUX> __device__ static void st(uint16_t v, rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, static_cast<int>(vo), static_cast<int>(so), AUX);
+  }
+};
+
+// Registers one thread holds for one z-plane of the pipeline: raw loaded
+// values, so that nothing waits on a load until the plane is consumed.  Every
+// vector-memory load of the z loop lives here: s_waitcnt vmcnt retires loads
+// in issue order, so a load consumed in the same iteration would also wait for
+// every prefetch issued before it.
+template <typename raw, int RY, int NYH, bool ADJ>
+struct Stage {
+  raw lead[RY];                 // A^n at plane z+R (enters the z queue)
+  raw p[RY];                    // A^{n-1} at plane z
+  float m[RY];                  // m at plane z
+  raw yh[NYH];                  // y-halo rows of A^n at plane z owned by this wavefront
+  raw xh;                       // x-halo value of A^n at plane z (lanes < 8*RY)
+  float gz;                     // sponge factor of plane z
+  float leadF[ADJ ? RY : 1];    // adjoint: forward field, same roles
+  float res[ADJ ? RY : 1];      // adjoint: residual injected at receivers of plane z
+  float yhF[ADJ ? NYH : 1];
+  float xhF;
+  float img[ADJ ? RY : 1];      // adjoint: imaging accumulator at plane z
+};
+
+constexpr int kQ = 2 * R + 1;  // z-queue length (planes z-4 .. z+4)
+
+// BY wavefronts per workgroup, RY consecutive rows per wavefront (tile 64 x
+// BY*RY), PD planes of loads in flight ahead of the plane being computed
+// (PD divides 9: the z loop is unrolled 9 times so the queue rotates by
+// register renaming instead of copies).
+template <int S, int BY, int RY, int PD, bool ADJ>
 __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   using C = Codec<S>;
   using raw = typename C::raw;
+  using B = Buf<raw>;
   constexpr int TY = BY * RY;
-  constexpr int NT = 64 * BY;
   constexpr int LW = kTileX + 2 * R;
   constexpr int LH = TY + 2 * R;
-  constexpr int HALO = 2 * R * kTileX + 2 * R * TY;
-  constexpr int HS = (HALO + NT - 1) / NT;
-  __shared__ float lds[2][LH * LW];
-  __shared__ float ldsF[ADJ ? 2 : 1][ADJ ? LH * LW : 1];
+  constexpr int NYH = (2 * R + BY - 1) / BY;
+  constexpr uint32_t ES = sizeof(raw);
+  static_assert(8 * RY <= 64, "x-halo of a wavefront's rows must fit in one load");
+  static_assert(kQ % PD == 0, "pipeline depth must divide the queue length");
+  // each LDS plane ends with a 64-float scratch row: halo writes of lanes or
+  // wavefronts with nothing to write go there, so no write is predicated
+  constexpr int LP = LH * LW + 64;
+  constexpr int DUMMY = LH * LW;
+  __shared__ float lds[2][LP];
+  __shared__ float ldsF[ADJ ? 2 : 1][ADJ ? LP : 1];
   __shared__ float red[BY];
 
   // XCD-aware tile order: hardware id b runs on XCD b % 8.
@@ -98,12 +165,15 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   const int x0 = tix * kTileX, y0 = tiy * TY;
   const int zb = chunk * a.zchunk;
   const int ze = min(zb + a.zchunk, a.nz);
-  const int lx = static_cast<int>(threadIdx.x), ly = static_cast<int>(threadIdx.y);
-  const int tid = ly * 64 + lx;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const size_t plane = static_cast<size_t>(nx) * static_cast<size_t>(ny);
-  const int x = x0 + lx;
+  const uint32_t pbytes = static_cast<uint32_t>(plane) * ES;
+  const uint32_t pbytes_f = static_cast<uint32_t>(plane) * 4u;
+  const int x = x0 + lane;
   const bool xin = x < nx;
+  const int yb = y0 + w * RY;  // first row of this wavefront
 
   // ---- step index and 16-bit field scales
   const int n = ADJ ? 0 : a.st->n + a.k;
@@ -118,203 +188,243 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
     const int e_next = scale_exponent(a.beta * acur + aprev + qmag);
     s_next = exp2i(e_next);
     inv_next = exp2i(-e_next);
-    if (logical == 0 && tid == 0) {
+    if (logical == 0 && threadIdx.x == 0) {
       a.st->exps[(n + 1) & 3] = e_next;
       a.st->amax[(n + 2) & 3] = 0u;
     }
   }
 
-  // ---- rows owned by this thread: y = y0 + ly + BY*j
-  int roff[RY];
-  bool rin[RY];
-  float gxy[RY];
+  // ---- per-row data (wavefront-uniform) and per-lane data
+  bool rowin[RY], ok[RY];
+  float gyv[RY];
   int ryi[RY];
-  int srcj = -1;
+  uint32_t rowo[RY], rowo_f[RY];  // byte offset of the (clamped) row in a plane
+  const uint32_t xl = static_cast<uint32_t>(min(x, nx - 1));
   const float gxv = xin ? a.gx[x] : 0.f;
   int rxi = -1;
   if (a.box.cnx > 0 && xin) {
     const int d = x - a.box.x0;
     if (d >= 0 && d % a.box.sx == 0 && d / a.box.sx < a.box.cnx) rxi = d / a.box.sx;
   }
+  int srcj = -1;
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
-    const int yj = y0 + ly + BY * j;
-    rin[j] = xin && yj < ny;
-    roff[j] = rin[j] ? yj * nx + x : 0;
-    gxy[j] = rin[j] ? gxv * a.gy[yj] : 0.f;
+    const int yj = yb + j;
+    rowin[j] = yj < ny;
+    ok[j] = rowin[j] && xin;
+    rowo[j] = static_cast<uint32_t>(min(yj, ny - 1)) * static_cast<uint32_t>(nx) * ES;
+    rowo_f[j] = static_cast<uint32_t>(min(yj, ny - 1)) * static_cast<uint32_t>(nx) * 4u;
+    gyv[j] = rowin[j] ? a.gy[yj] : 0.f;
     ryi[j] = -1;
-    if (rxi >= 0 && rin[j]) {
+    if (a.box.cnx > 0 && rowin[j]) {
       const int d = yj - a.box.y0;
       if (d >= 0 && d % a.box.sy == 0 && d / a.box.sy < a.box.cny) ryi[j] = d / a.box.sy;
     }
     if (!ADJ && a.sx >= 0 && x == a.sx && yj == a.sy) srcj = j;
   }
-
-  // ---- halo slots: LDS offset and in-plane global offset (-1: ghost zero)
-  int hl[HS], ho[HS];
+  const uint32_t vo = xl * ES, vo_f = xl * 4u;  // lane byte offsets
+  // y-halo rows of this wavefront: halo row r = w + BY*i (r < R above the tile, else below)
+  bool yhin[NYH], yhok[NYH];
+  int yhlds[NYH];
+  uint32_t yho[NYH], yho_f[NYH];
 #pragma unroll
-  for (int s = 0; s < HS; ++s) {
-    const int i = tid + s * NT;
-    hl[s] = -1;
-    ho[s] = -1;
-    if (i < 2 * R * kTileX) {  // rows above / below the tile
-      const int r = i / kTileX, c = i % kTileX;
-      const int lr = r < R ? r : TY + r;
-      const int gyy = y0 - R + lr, gxx = x0 + c;
-      hl[s] = lr * LW + R + c;
-      if (gyy >= 0 && gyy < ny && gxx < nx) ho[s] = gyy * nx + gxx;
-    } else if (i < HALO) {  // columns left / right of the tile
-      const int jj = i - 2 * R * kTileX;
-      const int r = jj / (2 * R), c = jj % (2 * R);
-      const int gxx = c < R ? x0 - R + c : x0 + kTileX + (c - R);
-      const int gyy = y0 + r;
-      hl[s] = (R + r) * LW + (c < R ? c : kTileX + c);
-      if (gxx >= 0 && gxx < nx && gyy < ny) ho[s] = gyy * nx + gxx;
-    }
+  for (int i = 0; i < NYH; ++i) {
+    const int r = w + BY * i;
+    yhin[i] = r < 2 * R;
+    const int lr = r < R ? r : TY + r;
+    const int gyy = y0 - R + lr;
+    yhok[i] = yhin[i] && gyy >= 0 && gyy < ny && xin;
+    yhlds[i] = yhin[i] ? lr * LW + R : DUMMY;
+    const uint32_t row = static_cast<uint32_t>(min(max(gyy, 0), ny - 1)) * static_cast<uint32_t>(nx);
+    yho[i] = row * ES;
+    yho_f[i] = row * 4u;
+  }
+  // x-halo: lane l < 8*RY covers row l/8 of this wavefront, column l%8
+  int xhlds = DUMMY + lane;
+  bool xhok = false;
+  uint32_t xho = 0, xho_f = 0;
+  if (lane < 8 * RY) {
+    const int j = lane >> 3, c = lane & 7;
+    const int gxx = c < R ? x0 - R + c : x0 + kTileX + (c - R);
+    const int yj = yb + j;
+    xhlds = (R + w * RY + j) * LW + (c < R ? c : kTileX + c);
+    xhok = gxx >= 0 && gxx < nx && yj < ny;
+    const uint32_t e = static_cast<uint32_t>(min(yj, ny - 1)) * static_cast<uint32_t>(nx) +
+                       static_cast<uint32_t>(min(max(gxx, 0), nx - 1));
+    xho = e * ES;
+    xho_f = e * 4u;
   }
 
   const raw *U = static_cast<const raw *>(a.cur);
   const raw *P = static_cast<const raw *>(a.prev);
   raw *O = static_cast<raw *>(a.out);
 
-  // ---- prologue: queue planes zb-4 .. zb+3, lead plane zb+4, halo/prev/m of plane zb
-  float q[2 * R + 1][RY];
-  float qF[ADJ ? 2 * R + 1 : 1][RY];
-  float lead[RY], leadF[RY], hal[HS], halF[HS], pv[RY], mv[RY], iv[RY];
+  auto rec_plane = [&](int z) {  // receiver-box index of plane z, or -1
+    int rzi = -1;
+    if (a.box.cnx > 0) {
+      const int d = z - a.box.z0;
+      if (d >= 0 && d % a.box.sz == 0 && d / a.box.sz < a.box.cnz) rzi = d / a.box.sz;
+    }
+    return rzi;
+  };
+  const rsrc_t rgz = make_rsrc(a.gz, static_cast<uint32_t>(nz) * 4u);
+  // residual row of this launch (adjoint); the resource covers exactly that row
+  const rsrc_t rres = ADJ ? make_rsrc(a.resid + static_cast<size_t>(a.resid_row) * a.nrec,
+                                      static_cast<uint32_t>(a.nrec) * 4u)
+                          : make_rsrc(a.gz, 4u);
+
+  using StageT = Stage<raw, RY, NYH, ADJ>;
+  auto load_stage = [&](StageT &st, int z) {
+    const size_t zc = static_cast<size_t>(z) * plane;
+    const size_t zl = static_cast<size_t>(min(z + R, nz - 1)) * plane;
+    st.gz = Buf<float>::ld<0>(rgz, 0u, static_cast<uint32_t>(z) * 4u);
+    const rsrc_t rl = make_rsrc(U + zl, pbytes);
+    const rsrc_t rc = make_rsrc(U + zc, pbytes);
+    const rsrc_t rp = make_rsrc(P + zc, pbytes);
+    const rsrc_t rm = make_rsrc(a.m + zc, pbytes_f);
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      st.lead[j] = B::template ld<0>(rl, vo, rowo[j]);
+      st.p[j] = B::template ld<kNT>(rp, vo, rowo[j]);
+      st.m[j] = Buf<float>::ld<kNT>(rm, vo_f, rowo_f[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < NYH; ++i) st.yh[i] = B::template ld<0>(rc, vo, yho[i]);
+    st.xh = B::template ld<0>(rc, xho, 0);
+    if (ADJ) {
+      const rsrc_t fl = make_rsrc(a.fwd + zl, pbytes_f);
+      const rsrc_t fc = make_rsrc(a.fwd + zc, pbytes_f);
+      const rsrc_t ri = make_rsrc(a.img + zc, pbytes_f);
+#pragma unroll
+      for (int j = 0; j < RY; ++j) {
+        st.leadF[j] = Buf<float>::ld<0>(fl, vo_f, rowo_f[j]);
+        st.img[j] = Buf<float>::ld<kNT>(ri, vo_f, rowo_f[j]);
+      }
+#pragma unroll
+      for (int i = 0; i < NYH; ++i) st.yhF[i] = Buf<float>::ld<0>(fc, vo_f, yho_f[i]);
+      st.xhF = Buf<float>::ld<0>(fc, xho_f, 0);
+      const int rzi = rec_plane(z);
+#pragma unroll
+      for (int j = 0; j < RY; ++j) {
+        const bool at = rzi >= 0 && ryi[j] >= 0 && rxi >= 0;
+        const uint32_t ridx = at ? static_cast<uint32_t>((rzi * a.box.cny + ryi[j]) * a.box.cnx + rxi) : 0u;
+        st.res[j] = Buf<float>::ld<0>(rres, ridx * 4u, 0u);
+      }
+    }
+  };
+
+  // ---- prologue: queue slot (p - zb + R) mod 9 holds plane p; stages hold planes zb .. zb+PD-1
+  float q[kQ][RY];
+  float qF[ADJ ? kQ : 1][RY];
 #pragma unroll
   for (int i = 0; i < 2 * R; ++i) {
     const int zz = zb - R + i;
     const bool zok = zz >= 0 && zz < nz;
-    const size_t zo = zok ? static_cast<size_t>(zz) * plane : 0;
+    const rsrc_t r = make_rsrc(U + static_cast<size_t>(min(max(zz, 0), nz - 1)) * plane, pbytes);
+    const rsrc_t rf = make_rsrc(a.fwd + static_cast<size_t>(min(max(zz, 0), nz - 1)) * plane, pbytes_f);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      q[i][j] = (zok && rin[j]) ? C::dec(U[zo + roff[j]]) * inv_cur : 0.f;
-      if (ADJ) qF[i][j] = (zok && rin[j]) ? a.fwd[zo + roff[j]] : 0.f;
+      const float u = C::dec(B::template ld<0>(r, vo, rowo[j])) * inv_cur;
+      q[i][j] = (zok && ok[j]) ? u : 0.f;
+      if (ADJ) {
+        const float f = Buf<float>::ld<0>(rf, vo_f, rowo_f[j]);
+        qF[i][j] = (zok && ok[j]) ? f : 0.f;
+      }
     }
   }
-  {
-    const int zz = zb + R;
-    const bool zok = zz < nz;
-    const size_t zo = zok ? static_cast<size_t>(zz) * plane : 0;
-    const size_t zc = static_cast<size_t>(zb) * plane;
+  StageT stg[PD];
 #pragma unroll
-    for (int j = 0; j < RY; ++j) {
-      lead[j] = (zok && rin[j]) ? C::dec(U[zo + roff[j]]) * inv_cur : 0.f;
-      if (ADJ) leadF[j] = (zok && rin[j]) ? a.fwd[zo + roff[j]] : 0.f;
-      pv[j] = rin[j] ? C::dec(ld_stream(P + zc + roff[j])) * inv_prev : 0.f;
-      mv[j] = rin[j] ? ld_stream(a.m + zc + roff[j]) : 0.f;
-      if (ADJ) iv[j] = rin[j] ? ld_stream(a.img + zc + roff[j]) : 0.f;
-    }
-#pragma unroll
-    for (int s = 0; s < HS; ++s) {
-      hal[s] = ho[s] >= 0 ? C::dec(U[zc + ho[s]]) * inv_cur : 0.f;
-      if (ADJ) halF[s] = ho[s] >= 0 ? a.fwd[zc + ho[s]] : 0.f;
-    }
-  }
+  for (int s = 0; s < PD; ++s)
+    if (zb + s < ze) load_stage(stg[s], zb + s);
 
   const float wsrc = (!ADJ && a.sx >= 0) ? a.wavelet[n] * a.src_scale : 0.f;
   float amax_loc = 0.f;
 
-  for (int z = zb; z < ze; ++z) {
+  for (int zs = zb; zs < ze; zs += kQ) {
 #pragma unroll
-    for (int j = 0; j < RY; ++j) {
-      q[2 * R][j] = lead[j];
-      if (ADJ) qF[2 * R][j] = leadF[j];
-    }
-    float *L = lds[z & 1];
-    float *LF = ldsF[ADJ ? (z & 1) : 0];
-#pragma unroll
-    for (int j = 0; j < RY; ++j) {
-      L[(R + ly + BY * j) * LW + R + lx] = q[R][j];
-      if (ADJ) LF[(R + ly + BY * j) * LW + R + lx] = qF[R][j];
-    }
-#pragma unroll
-    for (int s = 0; s < HS; ++s) {
-      if (hl[s] >= 0) {
-        L[hl[s]] = hal[s];
-        if (ADJ) LF[hl[s]] = halF[s];
-      }
-    }
-    float pc[RY], mc[RY], ic[RY];
-#pragma unroll
-    for (int j = 0; j < RY; ++j) {
-      pc[j] = pv[j];
-      mc[j] = mv[j];
-      ic[j] = ADJ ? iv[j] : 0.f;
-    }
-    if (z + 1 < ze) {  // prefetch plane z+1 (lead plane z+1+R)
-      const int zz = z + 1 + R;
-      const bool zok = zz < nz;
-      const size_t zo = zok ? static_cast<size_t>(zz) * plane : 0;
-      const size_t zc = static_cast<size_t>(z + 1) * plane;
+    for (int s = 0; s < kQ; ++s) {
+      const int z = zs + s;
+      if (z >= ze) break;
+      const int cslot = (s + R) % kQ;          // plane z
+      StageT &cs = stg[s % PD];
+      float *L = lds[(z - zb) & 1];
+      float *LF = ldsF[ADJ ? ((z - zb) & 1) : 0];
+      const bool lok = z + R < nz;
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
-        lead[j] = (zok && rin[j]) ? C::dec(U[zo + roff[j]]) * inv_cur : 0.f;
-        if (ADJ) leadF[j] = (zok && rin[j]) ? a.fwd[zo + roff[j]] : 0.f;
-        pv[j] = rin[j] ? C::dec(ld_stream(P + zc + roff[j])) * inv_prev : 0.f;
-        mv[j] = rin[j] ? ld_stream(a.m + zc + roff[j]) : 0.f;
-        if (ADJ) iv[j] = rin[j] ? ld_stream(a.img + zc + roff[j]) : 0.f;
-      }
-#pragma unroll
-      for (int s = 0; s < HS; ++s) {
-        hal[s] = ho[s] >= 0 ? C::dec(U[zc + ho[s]]) * inv_cur : 0.f;
-        if (ADJ) halF[s] = ho[s] >= 0 ? a.fwd[zc + ho[s]] : 0.f;
-      }
-    }
-    __syncthreads();
-
-    const float gzv = a.gz[z];
-    const size_t zc = static_cast<size_t>(z) * plane;
-    int rzi = -1;
-    if (rxi >= 0) {
-      const int d = z - a.box.z0;
-      if (d >= 0 && d % a.box.sz == 0 && d / a.box.sz < a.box.cnz) rzi = d / a.box.sz;
-    }
-#pragma unroll
-    for (int j = 0; j < RY; ++j) {
-      const float *row = L + (R + ly + BY * j) * LW + R + lx;
-      const float c = q[R][j];
-      float lap = a.c.k0 * c;
-#pragma unroll
-      for (int m = 1; m <= R; ++m) {
-        lap = fmaf(a.c.kx[m - 1], row[m] + row[-m], lap);
-        lap = fmaf(a.c.ky[m - 1], row[m * LW] + row[-m * LW], lap);
-        lap = fmaf(a.c.kz[m - 1], q[R + m][j] + q[R - m][j], lap);
-      }
-      const bool at_rec = rzi >= 0 && ryi[j] >= 0;
-      const int ridx = at_rec ? (rzi * a.box.cny + ryi[j]) * a.box.cnx + rxi : 0;
-      if (ADJ && at_rec) lap += a.resid[static_cast<size_t>(a.resid_row) * a.nrec + ridx];
-      const float g = gxy[j] * gzv;
-      float v = fmaf(-g, pc[j], 2.f * c);
-      v = fmaf(mc[j], lap, v);
-      if (!ADJ && srcj == j && z == a.sz) v += wsrc;
-      v *= g;
-      if (rin[j]) {
-        const raw r = C::enc(v * s_next);
-        st_stream(r, O + zc + roff[j]);
-        const float stored = C::dec(r);
-        if (S != kF32) amax_loc = fmaxf(amax_loc, fabsf(stored));
-        if (!ADJ && at_rec) a.traces[static_cast<size_t>(n) * a.nrec + ridx] = stored * inv_next;
+        q[(s + 2 * R) % kQ][j] = (ok[j] && lok) ? C::dec(cs.lead[j]) * inv_cur : 0.f;
+        L[(R + w * RY + j) * LW + R + lane] = q[cslot][j];
         if (ADJ) {
-          const float *rowF = LF + (R + ly + BY * j) * LW + R + lx;
-          const float cF = qF[R][j];
-          float lapF = a.c.k0 * cF;
-#pragma unroll
-          for (int m = 1; m <= R; ++m) {
-            lapF = fmaf(a.c.kx[m - 1], rowF[m] + rowF[-m], lapF);
-            lapF = fmaf(a.c.ky[m - 1], rowF[m * LW] + rowF[-m * LW], lapF);
-            lapF = fmaf(a.c.kz[m - 1], qF[R + m][j] + qF[R - m][j], lapF);
-          }
-          st_stream(fmaf(c, lapF, ic[j]), a.img + zc + roff[j]);
+          qF[(s + 2 * R) % kQ][j] = (ok[j] && lok) ? cs.leadF[j] : 0.f;
+          LF[(R + w * RY + j) * LW + R + lane] = qF[cslot][j];
         }
       }
-    }
 #pragma unroll
-    for (int i = 0; i < 2 * R; ++i) {
+      for (int i = 0; i < NYH; ++i) {
+        L[yhlds[i] + lane] = yhok[i] ? C::dec(cs.yh[i]) * inv_cur : 0.f;
+        if (ADJ) LF[yhlds[i] + lane] = yhok[i] ? cs.yhF[i] : 0.f;
+      }
+      L[xhlds] = xhok ? C::dec(cs.xh) * inv_cur : 0.f;
+      if (ADJ) LF[xhlds] = xhok ? cs.xhF : 0.f;
+      float pc[RY], mc[RY], ic[RY], rc[RY];
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
-        q[i][j] = q[i + 1][j];
-        if (ADJ) qF[i][j] = qF[i + 1][j];
+        pc[j] = C::dec(cs.p[j]) * inv_prev;
+        mc[j] = cs.m[j];
+        ic[j] = ADJ ? cs.img[j] : 0.f;
+        rc[j] = ADJ ? cs.res[j] : 0.f;
+      }
+      const float gzv = cs.gz;
+      load_stage(cs, min(z + PD, ze - 1));  // past the chunk end: a repeat of the last plane, unused
+      __syncthreads();
+
+      const size_t zc = static_cast<size_t>(z) * plane;
+      const rsrc_t ro = make_rsrc(O + zc, pbytes);
+      const int rzi = rec_plane(z);
+#pragma unroll
+      for (int j = 0; j < RY; ++j) {
+        const float *row = L + (R + w * RY + j) * LW + R + lane;
+        const float c = q[cslot][j];
+        float lap = a.c.k0 * c;
+#pragma unroll
+        for (int m = 1; m <= R; ++m) {
+          // y neighbours come from this thread's own rows when they lie in the strip
+          const float yp = (j + m < RY) ? q[cslot][(j + m) % RY] : row[m * LW];
+          const float ym = (j - m >= 0) ? q[cslot][(j - m + RY) % RY] : row[-m * LW];
+          lap = fmaf(a.c.kx[m - 1], row[m] + row[-m], lap);
+          lap = fmaf(a.c.ky[m - 1], yp + ym, lap);
+          lap = fmaf(a.c.kz[m - 1], q[(s + R + m) % kQ][j] + q[(s + R - m + kQ) % kQ][j], lap);
+        }
+        const bool at_rec = rzi >= 0 && ryi[j] >= 0 && rxi >= 0;
+        const int ridx = at_rec ? (rzi * a.box.cny + ryi[j]) * a.box.cnx + rxi : 0;
+        if (ADJ && at_rec) lap += rc[j];
+        const float g = gxv * (gyv[j] * gzv);
+        float v = fmaf(-g, pc[j], 2.f * c);
+        v = fmaf(mc[j], lap, v);
+        if (!ADJ && srcj == j && z == a.sz) v += wsrc;
+        v *= g;
+        if (ok[j]) {
+          const raw r = C::enc(v * s_next);
+          B::template st<kNT>(r, ro, vo, rowo[j]);
+          const float stored = C::dec(r);
+          if (S != kF32) amax_loc = fmaxf(amax_loc, fabsf(stored));
+          if (!ADJ && at_rec) a.traces[static_cast<size_t>(n) * a.nrec + ridx] = stored * inv_next;
+          if (ADJ) {
+            const float *rowF = LF + (R + w * RY + j) * LW + R + lane;
+            const float cF = qF[cslot][j];
+            float lapF = a.c.k0 * cF;
+#pragma unroll
+            for (int m = 1; m <= R; ++m) {
+              const float yp = (j + m < RY) ? qF[cslot][(j + m) % RY] : rowF[m * LW];
+              const float ym = (j - m >= 0) ? qF[cslot][(j - m + RY) % RY] : rowF[-m * LW];
+              lapF = fmaf(a.c.kx[m - 1], rowF[m] + rowF[-m], lapF);
+              lapF = fmaf(a.c.ky[m - 1], yp + ym, lapF);
+              lapF = fmaf(a.c.kz[m - 1], qF[(s + R + m) % kQ][j] + qF[(s + R - m + kQ) % kQ][j], lapF);
+            }
+            const rsrc_t ri = make_rsrc(a.img + zc, pbytes_f);
+            Buf<float>::st<kNT>(fmaf(c, lapF, ic[j]), ri, vo_f, rowo_f[j]);
+          }
+        }
       }
     }
   }
@@ -322,12 +432,12 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   if (S != kF32) {  // one order-independent atomic per workgroup
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) amax_loc = fmaxf(amax_loc, __shfl_xor(amax_loc, off, 64));
-    if (lx == 0) red[ly] = amax_loc;
+    if (lane == 0) red[w] = amax_loc;
     __syncthreads();
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
       float mx = red[0];
 #pragma unroll
-      for (int w = 1; w < BY; ++w) mx = fmaxf(mx, red[w]);
+      for (int k = 1; k < BY; ++k) mx = fmaxf(mx, red[k]);
       atomicMax(&a.st->amax[(n + 1) & 3], __float_as_uint(mx));
     }
   }
@@ -454,26 +564,29 @@ unsigned grid_for(size_t n, unsigned block) {
   return static_cast<unsigned>(want < 1 ? 1 : (want > cap ? cap : want));
 }
 
-// (BY, RY) per variant
-constexpr Variant kVariants[] = {{4, 4}, {8, 4}, {4, 2}, {8, 2}, {2, 4}, {4, 8}};
+// (BY, RY, PD) per variant
+constexpr Variant kVariants[] = {{8, 4, 3}, {4, 8, 1}, {4, 4, 3}, {8, 2, 3},
+                                 {4, 4, 1}, {8, 4, 1}, {2, 8, 1}, {4, 2, 3}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <int S, int BY, int RY, bool ADJ>
+template <int S, int BY, int RY, int PD, bool ADJ>
 hipError_t launch_one(const StepArgs &a, hipStream_t s) {
   const unsigned grid = static_cast<unsigned>((a.total_tiles + 7) / 8 * 8);
-  hipLaunchKernelGGL((step_kernel<S, BY, RY, ADJ>), dim3(grid), dim3(64, BY), 0, s, a);
+  hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, ADJ>), dim3(grid), dim3(64 * BY), 0, s, a);
   return hipGetLastError();
 }
 
 template <int S, bool ADJ>
 hipError_t launch_variant(int v, const StepArgs &a, hipStream_t s) {
   switch (v) {
-    case 0: return launch_one<S, 4, 4, ADJ>(a, s);
-    case 1: return launch_one<S, 8, 4, ADJ>(a, s);
-    case 2: return launch_one<S, 4, 2, ADJ>(a, s);
-    case 3: return launch_one<S, 8, 2, ADJ>(a, s);
-    case 4: return launch_one<S, 2, 4, ADJ>(a, s);
-    case 5: return launch_one<S, 4, 8, ADJ>(a, s);
+    case 0: return launch_one<S, 8, 4, 3, ADJ>(a, s);
+    case 1: return launch_one<S, 4, 8, 1, ADJ>(a, s);
+    case 2: return launch_one<S, 4, 4, 3, ADJ>(a, s);
+    case 3: return launch_one<S, 8, 2, 3, ADJ>(a, s);
+    case 4: return launch_one<S, 4, 4, 1, ADJ>(a, s);
+    case 5: return launch_one<S, 8, 4, 1, ADJ>(a, s);
+    case 6: return launch_one<S, 2, 8, 1, ADJ>(a, s);
+    case 7: return launch_one<S, 4, 2, 3, ADJ>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -364,9 +364,11 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   w->tiles_y = (ny + TY - 1) / TY;
   int zc = p->zchunk;
   if (zc <= 0) {
+    // about one long-lived workgroup per CU (256 CUs): long z-chunks re-read
+    // fewer overlap planes and keep the prefetch pipeline full
     const int per_plane = w->tiles_x * w->tiles_y;
-    const int want = 2048;  // >= 8 workgroups per CU in flight
-    const int chunks = std::max(1, (want + per_plane - 1) / per_plane);
+    const int want = 256;
+    const int chunks = std::max(1, (want + per_plane / 2) / per_plane);
     zc = std::max(16, (nz + chunks - 1) / chunks);
   }
   w->zchunk = std::min(zc, nz);

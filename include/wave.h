@@ -65,7 +65,7 @@ enum wave_storage {
 enum { WAVE_FLAG_NONFINITE = 1u };
 
 typedef struct {
-  int32_t nx, ny, nz;        /* grid nodes per axis, >= 1 */
+  int32_t nx, ny, nz;        /* grid nodes per axis, >= 1; nx*ny < 2^29 */
   double dx, dy, dz;         /* grid spacing (m), > 0 */
   double dt;                 /* time step (s), > 0, at most the stability limit */
   int32_t sponge_width;      /* damping strip width in nodes; 0 = zero-Dirichlet only */

@@ -36,6 +36,7 @@ from .analytic import point_source_trace
 from .dense import dense_laplacian
 from .metrics import rel_l2, rel_max
 from .pointwise import step_at
+from . import storage
 
 __all__ = [
     "fd_coefficients", "second_derivative_weights", "laplacian", "sponge_profile", "sponge_field",

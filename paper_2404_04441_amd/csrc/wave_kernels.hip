@@ -268,10 +268,13 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
     return rzi;
   };
   const rsrc_t rgz = make_rsrc(a.gz, static_cast<uint32_t>(nz) * 4u);
-  // residual row of this launch (adjoint); the resource covers exactly that row
-  const rsrc_t rres = ADJ ? make_rsrc(a.resid + static_cast<size_t>(a.resid_row) * a.nrec,
-                                      static_cast<uint32_t>(a.nrec) * 4u)
-                          : make_rsrc(a.gz, 4u);
+  // residual row of this launch (adjoint); the resource covers exactly that
+  // row.  Its loads are unconditional, so without receivers it points at the
+  // (always valid) z table instead.
+  const bool has_res = ADJ && a.resid != nullptr && a.nrec > 0;
+  const rsrc_t rres = has_res ? make_rsrc(a.resid + static_cast<size_t>(a.resid_row) * a.nrec,
+                                          static_cast<uint32_t>(a.nrec) * 4u)
+                              : make_rsrc(a.gz, 4u);
 
   using StageT = Stage<raw, RY, NYH, ADJ>;
   auto load_stage = [&](StageT &st, int z) {

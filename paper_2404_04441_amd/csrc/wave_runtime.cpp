@@ -32,7 +32,8 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int validate(const wave_params *p) {
   if (!p) return WAVE_EINVAL;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return WAVE_EINVAL;
-  if (static_cast<int64_t>(p->nx) * p->ny >= (int64_t(1) << 31)) return WAVE_EINVAL;  // in-plane int offsets
+  // one xy plane of float32 must stay below 2^31 bytes (32-bit buffer offsets)
+  if (static_cast<int64_t>(p->nx) * p->ny >= (int64_t(1) << 29)) return WAVE_EINVAL;
   if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dz) || !finite_pos(p->dt)) return WAVE_EINVAL;
   if (p->sponge_width < 0 || !std::isfinite(p->sponge_alpha) || p->sponge_alpha < 0.0) return WAVE_EINVAL;
   if (p->storage < WAVE_F32 || p->storage > WAVE_BF16) return WAVE_EINVAL;
@@ -402,7 +403,7 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
     double kabs = 0.0;
     for (int m = 1; m <= 4; ++m) kabs += 2.0 * std::fabs(kC[m]) * (ix2 + iy2 + iz2);
     const double k0 = kC[0] * (ix2 + iy2 + iz2);
-    w->beta = static_cast<float>(std::max(2.0, std::fabs(2.0 + Mmax * k0) + Mmax * kabs) * (1.0 + 1e-6));
+    w->beta = static_cast<float>(std::max(2.0, std::fabs(2.0 + Mmax * k0) + Mmax * kabs));
   }
   if (!rc) rc = do_reset(w);
   if (rc) {

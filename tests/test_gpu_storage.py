@@ -1,0 +1,160 @@
+"""16-bit wavefield storage on the GPU.
+
+Parity: the HIP path against the oracle's emulation of the same storage
+scheme (power-of-two scale per field, round-to-nearest-even 16-bit storage,
+float32 vs float64 arithmetic in between).  Over one step the two agree
+exactly except for rare one-ulp flips where the unrounded float32 and float64
+values straddle a rounding boundary; over many steps the flips propagate, so
+the multi-step bound is set from the emulation's own float32-vs-float64
+sensitivity.
+
+Error against the unquantized FP64 oracle is reported (parity unpinned: no
+published value fixes it) with a loose sanity bound.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.storage import forward_stored
+from synth import COURANT, ricker, smooth_random, workload
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+# GPU vs emulation of the same scheme after 90 steps (rel-L2 of field and
+# traces).  Rounding decisions flip with last-bit differences of the
+# unrounded value, and the flips propagate: the oracle's own emulation run in
+# float32 instead of float64 arithmetic already differs by 1.1e-3 (f16) and
+# 5.3e-3 (bf16) on this case, so the bound is three times that floor.
+TOL_EMUL = {"f16": 3.5e-3, "bf16": 1.6e-2}
+# unquantized FP64 vs storage type on the 500-step 128^3 crop: the oracle's
+# own float32 loop sits at 1.9e-5 there; 16-bit bounds are sanity bounds only
+# (parity unpinned; measured f16 4.2e-2)
+BOUND_PLAIN = {"f32": 1e-4, "f16": 1e-1, "bf16": 5e-1}
+ULP = {"f16": 2.0 ** -10, "bf16": 2.0 ** -7}   # spacing relative to a normal value
+TINY = {"f16": 2.0 ** -24, "bf16": 2.0 ** -133}  # smallest subnormal
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def gpu_run(vel, h, dt, src, wavelet, rec, nt, **kw):
+    from paper_2404_04441_amd import Solver
+
+    s = Solver(torch.from_numpy(vel).cuda(), h, dt, src=src, rec=rec, **kw)
+    tr = s.run(nt, torch.from_numpy(wavelet).cuda())
+    u = s.read_field(0)
+    flags = s.sync_status()
+    out = dict(u=u.cpu().numpy(), traces=tr.cpu().numpy(), flags=flags)
+    s.close()
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def ragged():
+    shape = (37, 29, 71)
+    h = (10.0, 12.0, 9.0)
+    vel = smooth_random(shape, seed=51)
+    dt = COURANT * 9.0 / 4500.0
+    nt = 90
+    wav = ricker(nt, dt, 25.0)
+    rec = np.array([[x, y, 3] for y in range(0, 29, 4) for x in range(71)], dtype=np.int32)
+    src = (35, 14, 18)
+    plain = oracle.forward(vel, h, dt, src, wav, rec, nt=nt, sponge_width=5, sponge_alpha=0.05)
+    return shape, h, vel, dt, nt, wav, rec, src, plain
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_storage_matches_emulated_scheme(fmt):
+    shape, h, vel, dt, nt, wav, rec, src, plain = ragged()
+    _say(f"case: {fmt} storage, ragged {shape}, {nt} steps")
+    emu = forward_stored(vel, h, dt, src, wav, rec, nt, fmt, sponge_width=5, sponge_alpha=0.05)
+    got = gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05, storage=fmt)
+    e_emu = oracle.rel_l2(got["u"], emu["u"])
+    e_emu_tr = oracle.rel_l2(got["traces"], emu["traces"])
+    e_plain = oracle.rel_l2(got["u"], plain["u"])
+    e_emu_plain = oracle.rel_l2(emu["u"], plain["u"])
+    _say(f"{fmt}: gpu-vs-emulation u={e_emu:.3e} traces={e_emu_tr:.3e}; "
+         f"gpu-vs-fp64 {e_plain:.3e}; emulation-vs-fp64 {e_emu_plain:.3e}")
+    assert got["flags"] == 0
+    assert e_emu <= TOL_EMUL[fmt] and e_emu_tr <= TOL_EMUL[fmt]
+    assert e_plain <= BOUND_PLAIN[fmt]
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_one_step_encoding(fmt):
+    """From the GPU's own decoded fields A^n, A^{n-1}, the oracle computes one
+    step in FP64, picks the exponent from the growth bound and rounds: the
+    GPU's stored A^{n+1} must use the same exponent and equal that value
+    except for rare one-ulp flips (float32 vs float64 before rounding)."""
+    from oracle.storage import growth_bound_beta, quantize, scale_exponent
+    from paper_2404_04441_amd import Solver
+
+    shape, h, vel, dt, nt, wav, rec, src, _ = ragged()
+    s = Solver(torch.from_numpy(vel).cuda(), h, dt, src=src, rec=rec, sponge_width=5, sponge_alpha=0.05,
+               storage=fmt)
+    w = torch.from_numpy(wav).cuda()
+    tr = torch.zeros((nt, len(rec)), device="cuda")
+    s.reset()
+    s.step(40, w, tr)
+    A = s.read_field(0).cpu().numpy().astype(np.float64)
+    Am1 = s.read_field(1).cpu().numpy().astype(np.float64)
+    s.step(1, w, tr)
+    got = s.read_field(0).cpu().numpy().astype(np.float64)
+    s.close()
+    hx, hy, hz = h
+    G = oracle.sponge_field(shape, 5, 0.05)
+    M = (dt * vel.astype(np.float64)) ** 2
+    q = np.zeros(shape)
+    q[src[2], src[1], src[0]] = dt * dt * float(wav[40]) / (hx * hy * hz)
+    exact = G * (2 * A - G * Am1 + M * oracle.laplacian(A, h) + q)
+    beta = growth_bound_beta(float(vel.max()), h, dt)
+    e = scale_exponent(beta * np.abs(A).max() + np.abs(Am1).max() + abs(q).max())
+    emu = quantize(exact * 2.0 ** e, fmt) * 2.0 ** -e
+    scaled = got * 2.0 ** e
+    assert np.array_equal(quantize(scaled, fmt), scaled)  # values on the format's grid
+    # The kernel forms the update in unscaled float32 and scales afterwards, so
+    # tail values below float32's normal range (|A| < 2^-126) underflow there
+    # while float64 keeps them; they are compared only where |A| > 2^-100.
+    live = np.abs(exact) > 2.0 ** -100
+    diff = (got != emu) & live
+    frac = diff.sum() / live.sum()
+    step = np.maximum(ULP[fmt] * np.abs(emu * 2.0 ** e), TINY[fmt])
+    worst = (np.abs(got - emu) * 2.0 ** e / step)[live].max()
+    _say(f"{fmt}: exponent {e}, {diff.sum()} of {live.sum()} live values differ, worst {worst:.2f} ulp")
+    assert live.sum() > 1000
+    assert frac <= 1e-2 and worst <= 1.0 + 1e-9
+    assert np.abs(got[~live]).max(initial=0.0) <= 2.0 ** -99
+
+
+def test_precision_crop_error_report():
+    """The 128^3 crop of the 1024^3 workload, 500 steps, every storage type
+    against the unquantized FP64 oracle (the per-configuration error report)."""
+    W = workload("precision_crop")
+    vel = W.velocity()
+    wav = W.wavelet()
+    _say("case: 128^3 crop, 500 steps, FP64 oracle")
+    ref = oracle.forward(vel, W.h, W.dt, W.src, wav, W.rec, nt=W.nt)
+    for fmt in ("f32", "f16", "bf16"):
+        got = gpu_run(vel, W.h, W.dt, W.src, wav, W.rec, W.nt, storage=fmt)
+        e_u = oracle.rel_l2(got["u"], ref["u"])
+        e_t = oracle.rel_l2(got["traces"], ref["traces"])
+        _say(f"crop {fmt}: rel-L2 field {e_u:.3e} traces {e_t:.3e}")
+        assert got["flags"] == 0
+        assert e_u <= BOUND_PLAIN[fmt]
+
+
+def test_storage_tile_variants_bitwise_identical():
+    from paper_2404_04441_amd import variant_count
+
+    shape, h, vel, dt, nt, wav, rec, src, _ = ragged()
+    for fmt in ("f16", "bf16"):
+        base = gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05, storage=fmt)
+        for v in range(variant_count()):
+            _say(f"case: {fmt} variant {v}")
+            got = gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05, storage=fmt, variant=v,
+                          zchunk=11)
+            assert np.array_equal(got["u"], base["u"]) and np.array_equal(got["traces"], base["traces"])

@@ -380,3 +380,61 @@ def test_pointwise_step_equals_full_loop():
     pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
     got = oracle.step_at(pts, A_n, A_nm1, vel, h, dt, src=src, s_n=w[5], sponge_width=W, sponge_alpha=alpha)
     assert np.abs(got - nxt.ravel()).max() <= 1e-13 * np.abs(nxt).max()
+
+
+# ------------------------------------------------- 16-bit storage scheme
+
+def test_quantizers_round_to_nearest_even():
+    from oracle.storage import quantize
+    # half: 10 fraction bits, ulp(1) = 2^-10
+    assert quantize(1 + 2.0 ** -11, "f16") == 1.0
+    assert quantize(1 + 3 * 2.0 ** -11, "f16") == 1 + 2.0 ** -9
+    assert quantize(1 + 2.0 ** -11 + 2.0 ** -20, "f16") == 1 + 2.0 ** -10
+    assert quantize(65504.0, "f16") == 65504.0 and quantize(-3.0, "f16") == -3.0
+    # bfloat16: 7 fraction bits, ulp(1) = 2^-7
+    assert quantize(1 + 2.0 ** -8, "bf16") == 1.0
+    assert quantize(1 + 3 * 2.0 ** -8, "bf16") == 1 + 2.0 ** -6
+    assert quantize(1 + 2.0 ** -8 + 2.0 ** -16, "bf16") == 1 + 2.0 ** -7
+    assert quantize(2.0 ** 100 * (1 + 2.0 ** -8), "bf16") == 2.0 ** 100  # float32 range
+    assert quantize(-1.5, "bf16") == -1.5
+
+
+def test_scale_exponent_keeps_magnitudes_below_2_14():
+    from oracle.storage import scale_exponent
+    assert scale_exponent(1.0) == 13 and scale_exponent(0.75) == 14 and scale_exponent(0.0) == 0
+    rng = np.random.default_rng(5)
+    for b in 10.0 ** rng.uniform(-25, 25, 200):  # inside the clamp of the exponent
+        e = scale_exponent(b)
+        assert 2.0 ** 13 <= b * 2.0 ** e < 2.0 ** 14
+
+
+def test_one_step_growth_bound_holds():
+    """|A^{n+1}| <= beta max|A^n| + max|A^{n-1}| + |q| on random fields."""
+    from oracle.storage import growth_bound_beta
+    shape, h = (10, 11, 12), (10.0, 9.0, 11.0)
+    vel = smooth_random(shape, seed=8).astype(np.float64)
+    dt = COURANT * 9.0 / vel.max()
+    beta = growth_bound_beta(vel.max(), h, dt)
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        A = rng.standard_normal(shape)
+        Am1 = rng.standard_normal(shape)
+        new = 2 * A - Am1 + (dt * vel) ** 2 * laplacian(A, h)
+        assert np.abs(new).max() <= beta * np.abs(A).max() + np.abs(Am1).max()
+
+
+def test_stored_scheme_without_rounding_is_the_plain_loop():
+    from oracle.storage import forward_stored
+    shape, h = (14, 13, 15), 10.0
+    vel = smooth_random(shape, seed=9)
+    dt = COURANT * h / 4500.0
+    from synth import ricker
+    w = ricker(60, dt, 30.0)
+    rec = np.array([[x, 6, 3] for x in range(15)])
+    a = forward_stored(vel, h, dt, (7, 6, 7), w, rec, 60, "none", sponge_width=3, sponge_alpha=0.1)
+    b = oracle.forward(vel, h, dt, (7, 6, 7), w, rec, nt=60, sponge_width=3, sponge_alpha=0.1)
+    assert np.abs(a["u"] - b["u"]).max() <= 1e-13 * np.abs(b["u"]).max()
+    assert np.abs(a["traces"] - b["traces"]).max() <= 1e-13 * np.abs(b["traces"]).max()
+    for fmt, tol in (("f16", 5e-3), ("bf16", 5e-2)):
+        q = forward_stored(vel, h, dt, (7, 6, 7), w, rec, 60, fmt, sponge_width=3, sponge_alpha=0.1)
+        assert 0 < oracle.rel_l2(q["u"], b["u"]) < tol

@@ -66,6 +66,22 @@ def cpu_baseline(W, vel):
                       f"single thread, {t:.1f} s; host has {os.cpu_count()} CPUs"}
 
 
+def serving_leg(count: int) -> dict:
+    """Serve the first `count` requests of the seeded Poisson stream (20 req/s;
+    grids 128^3 .. 384^3, 500..2000 steps, f32 or f16 storage)."""
+    from paper_2404_04441_amd.serve import GpuBackend, ShotServer, requests_from_workload, summarize
+
+    reqs = requests_from_workload(count)
+    print(f"[bench] serving {count} shot requests", file=sys.stderr, flush=True)
+    server = ShotServer(GpuBackend(graph_steps=20), budget_bytes=200 << 30, max_slots=8, chunk_steps=200)
+    res = server.run(reqs)
+    out = summarize(res, reqs, server.elapsed)
+    out["max_concurrent"] = server.max_concurrent
+    out["workload"] = f"first {count} of 512 Poisson shot requests at 20/s"
+    print(f"[bench] serving done: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +92,8 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--nt", type=int, default=0, help="time steps per shot (default: the workload's 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=64,
+                    help="requests of the Poisson shot stream to serve after the throughput run (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -167,6 +185,8 @@ def main():
                      "algorithmic_bytes_per_launch": bpp * W.npts},
         "nonfinite": bool(flags),
     }
+    if args.serving > 0:
+        out["serving"] = serving_leg(args.serving)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W, vel)

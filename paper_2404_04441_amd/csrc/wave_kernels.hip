@@ -23,12 +23,25 @@
 //    y-halo re-reads inside one XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "wave_internal.h"
 
 namespace wave {
 namespace {
 
 constexpr int R = kRadius;
+
+// f(std::integral_constant<int, 0>) ... f(std::integral_constant<int, N-1>):
+// a loop whose index is a compile-time constant in every iteration.
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 __device__ __forceinline__ float exp2i(int e) {  // 2^e, e in [-126, 127]
   return __uint_as_float(static_cast<uint32_t>(e + 127) << 23);
@@ -344,14 +357,23 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   float amax_loc = 0.f;
 
   for (int zs = zb; zs < ze; zs += kQ) {
-#pragma unroll
-    for (int s = 0; s < kQ; ++s) {
-      const int z = zs + s;
-      if (z >= ze) break;
+    // nine planes per trip with compile-time queue slots and stage indices, so
+    // the queue rotates by register renaming (a runtime index would move the
+    // queue into scratch memory)
+    // Positions past the chunk end (only in a trip that straddles it) run on
+    // clamped in-bounds planes with their stores switched off: no position is
+    // skipped, so no control-flow join makes the compiler drain the loads.
+    static_for<kQ>([&](auto sc) __attribute__((always_inline)) {
+      constexpr int s = decltype(sc)::value;
+      const int z = min(zs + s, ze - 1);
+      const bool live = zs + s < ze;
       const int cslot = (s + R) % kQ;          // plane z
       StageT &cs = stg[s % PD];
-      float *L = lds[(z - zb) & 1];
-      float *LF = ldsF[ADJ ? ((z - zb) & 1) : 0];
+      // buffer parity follows the unclamped position: consecutive positions
+      // must alternate even when the plane index is clamped
+      const int par = (zs + s - zb) & 1;
+      float *L = lds[par];
+      float *LF = ldsF[ADJ ? par : 0];
       const bool lok = z + R < nz;
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
@@ -406,7 +428,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
         v = fmaf(mc[j], lap, v);
         if (!ADJ && srcj == j && z == a.sz) v += wsrc;
         v *= g;
-        if (ok[j]) {
+        if (ok[j] && live) {
           const raw r = C::enc(v * s_next);
           B::template st<kNT>(r, ro, vo, rowo[j]);
           const float stored = C::dec(r);
@@ -429,7 +451,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
           }
         }
       }
-    }
+    });
   }
 
   if (S != kF32) {  // one order-independent atomic per workgroup

@@ -370,7 +370,8 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
     const int per_plane = w->tiles_x * w->tiles_y;
     const int want = 256;
     const int chunks = std::max(1, (want + per_plane / 2) / per_plane);
-    zc = std::max(16, (nz + chunks - 1) / chunks);
+    zc = std::max(18, (nz + chunks - 1) / chunks);
+    zc = (zc + 8) / 9 * 9;  // the kernel advances nine planes per trip
   }
   w->zchunk = std::min(zc, nz);
   w->nchunks = (nz + w->zchunk - 1) / w->zchunk;

@@ -6,11 +6,11 @@ solver's arithmetic (no stencil, no time stepping, no damping, no stability
 analysis).  Both sides receive the same float32 arrays produced here; the
 oracle promotes them to float64, the HIP path consumes them as they are.
 """
-from .velocity import smooth_random, layered_perturbed, two_layer, smooth_along_z, request_layered
+from .velocity import smooth_random, layered_perturbed, two_layer, smooth_along_z, request_layered, layered_profile
 from .wavelet import ricker
 from .workloads import Workload, workload, WORKLOADS, COURANT
 
 __all__ = [
-    "smooth_random", "layered_perturbed", "two_layer", "smooth_along_z", "request_layered",
+    "smooth_random", "layered_perturbed", "two_layer", "smooth_along_z", "request_layered", "layered_profile",
     "ricker", "Workload", "workload", "WORKLOADS", "COURANT",
 ]

@@ -128,14 +128,19 @@ def smooth_along_z(v: np.ndarray, sigma_cells: float) -> np.ndarray:
     return gaussian_filter1d(v.astype(np.float64), sigma_cells, axis=0, mode="nearest").astype(np.float32)
 
 
-def request_layered(shape, seed: int) -> np.ndarray:
-    """2..6 flat layers at random sorted depths with sorted velocities drawn
-    from U[1500, 4500] m/s (one serving request's model)."""
-    nz, ny, nx = shape
+def layered_profile(nz: int, seed: int) -> np.ndarray:
+    """z profile of a serving request's model: 2..6 flat layers at random
+    sorted depths with sorted velocities drawn from U[1500, 4500] m/s."""
     rng = np.random.default_rng(seed)
     nlayers = int(rng.integers(2, 7))
     depths = np.sort(rng.choice(np.arange(1, nz), size=nlayers - 1, replace=False))
     vels = np.sort(rng.uniform(V_MIN, V_MAX, size=nlayers))
     zi = np.searchsorted(depths, np.arange(nz), side="right")
-    v = vels[zi].astype(np.float32)
+    return vels[zi].astype(np.float32)
+
+
+def request_layered(shape, seed: int) -> np.ndarray:
+    """The full 3D model of :func:`layered_profile`."""
+    nz, ny, nx = shape
+    v = layered_profile(nz, seed)
     return np.broadcast_to(v[:, None, None], shape).copy()

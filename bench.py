@@ -51,19 +51,159 @@ def measured_traffic(storage: str):
 
 
 def cpu_baseline(W, vel):
-    import numpy as np
+    """The oracle as it is (NumPy, FP64, one thread) on a bounded sample of the
+    same workload: enough time steps of the full 512^3 grid for ~10 s."""
+    import math
 
     import oracle
 
-    steps = 1
-    wav = W.wavelet(steps)
-    t0 = time.perf_counter()
-    oracle.forward(vel, W.h, W.dt, W.src, wav, W.rec, nt=steps, sponge_width=W.sponge_width,
-                   sponge_alpha=W.sponge_alpha)
-    t = time.perf_counter() - t0
+    def timed(steps):
+        wav = W.wavelet(steps)
+        t0 = time.perf_counter()
+        oracle.forward(vel, W.h, W.dt, W.src, wav, W.rec, nt=steps, sponge_width=W.sponge_width,
+                       sponge_alpha=W.sponge_alpha)
+        return time.perf_counter() - t0
+
+    t1 = timed(1)
+    steps = 1 if t1 >= 10.0 else min(8, math.ceil(10.0 / t1))
+    t = timed(steps) if steps > 1 else t1
     return {"value": round(W.npts * steps / t / 1e9, 5), "unit": "Gpts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} time step of the {W.name} workload (sponge, source, receivers), FP64 NumPy, "
-                      f"single thread, {t:.1f} s; host has {os.cpu_count()} CPUs"}
+            "sample": f"{steps} time steps of the {W.name} workload (sponge, source, 512x512 receivers), "
+                      f"FP64 NumPy oracle, single thread, {t:.1f} s; host reports {os.cpu_count()} CPUs"}
+
+
+def stream_ceiling(dev, n: int) -> dict:
+    """What plain streams of the step's size reach on this GPU: a device copy
+    (1 read + 1 write) and torch.addcmul d = a + b * c (3 reads + 1 write, the
+    step's traffic pattern), both over n float32 elements."""
+    import torch
+
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.ones_like(a)
+    c = torch.ones_like(a)
+    d = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: d.copy_(a), 8 * n),
+                             ("addcmul_3r1w", lambda: torch.addcmul(a, b, c, out=d), 16 * n)):
+        for _ in range(3):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        out[f"{name}_gb_per_s"] = round(nbytes / ms / 1e6, 1)
+    del a, b, c, d
+    torch.cuda.empty_cache()
+    return out
+
+
+def kernel_rate(s, nt, wav, traces, npts, bpp):
+    """Average step-kernel time (events on the solver's stream) -> Gpts/s, GB/s."""
+    import torch
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    s.reset()
+    e0.record(s.stream)
+    s.step(nt, wav, traces)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / nt
+    return {"kernel_ms": round(ms, 4), "gpts_per_s": round(npts / ms / 1e6, 2),
+            "gb_per_s": round(bpp * npts / ms / 1e6, 1), "roofline_frac": round(bpp * npts / ms / 1e6 / PEAK_HBM_GBS, 4)}
+
+
+def storage_forms_leg(W, vel_dev, nt: int) -> dict:
+    """The 512^3 workload with 16-bit wavefield storage (float32 arithmetic)."""
+    import torch
+
+    from paper_2404_04441_amd import Solver
+
+    out = {}
+    wav = torch.from_numpy(W.wavelet(nt)).to(vel_dev.device)
+    traces = torch.empty((nt, len(W.rec)), dtype=torch.float32, device=vel_dev.device)
+    for fmt in ("f16", "bf16"):
+        s = Solver(vel_dev, W.h, W.dt, src=W.src, rec=W.rec, sponge_width=W.sponge_width,
+                   sponge_alpha=W.sponge_alpha, storage=fmt)
+        s.run(20, wav, traces)
+        out[fmt] = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT[fmt])
+        s.close()
+    return out
+
+
+def precision_leg(nt: int = 500) -> dict:
+    """The 1024^3 workload (smooth random model, 500 steps) in each storage type."""
+    import torch
+
+    from paper_2404_04441_amd import Solver
+    from synth import workload
+    from synth.velocity import smooth_random_torch
+
+    W = workload("precision")
+    dev = torch.device("cuda:0")
+    vel = smooth_random_torch(W.shape, seed=3, device=dev)
+    wav = torch.from_numpy(W.wavelet(nt)).to(dev)
+    traces = torch.empty((nt, len(W.rec)), dtype=torch.float32, device=dev)
+    out = {"workload": f"{W.name}, {nt} steps, Dirichlet, line of 1024 receivers"}
+    for fmt in ("f32", "f16", "bf16"):
+        s = Solver(vel, W.h, W.dt, src=W.src, rec=W.rec, storage=fmt)
+        s.run(10, wav, traces)
+        out[fmt] = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT[fmt])
+        s.close()
+        print(f"[bench] precision 1024^3 {fmt}: {out[fmt]}", file=sys.stderr, flush=True)
+    del vel
+    torch.cuda.empty_cache()
+    return out
+
+
+def gradient_leg() -> dict:
+    """The 256^3 two-layer gradient workload (800 steps, sqrt(T) checkpoints):
+    time of the velocity gradient against the time of the forward run."""
+    import time as _t
+
+    import numpy as np
+    import torch
+
+    from paper_2404_04441_amd import Solver
+    from synth import workload
+    from synth.velocity import smooth_along_z
+
+    W = workload("gradient")
+    dev = torch.device("cuda:0")
+    v_true = W.velocity()
+    v0 = smooth_along_z(v_true, 8.0)
+    wav = torch.from_numpy(W.wavelet()).to(dev)
+    st = Solver(torch.from_numpy(v_true).to(dev), W.h, W.dt, src=W.src, rec=W.rec)
+    d_obs = st.run(W.nt, wav).clone()
+    st.close()
+    s = Solver(torch.from_numpy(v0).to(dev), W.h, W.dt, src=W.src, rec=W.rec, adjoint=True, nt_max=W.nt)
+    tr = s.run(W.nt, wav)
+    resid = (tr - d_obs).contiguous()
+    grad = s.adjoint(W.nt, wav, resid)  # warm-up
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for _ in range(3):
+        s.run(W.nt, wav, tr)
+    torch.cuda.synchronize()
+    t_fwd = (_t.perf_counter() - t0) / 3
+    t0 = _t.perf_counter()
+    for _ in range(3):
+        s.adjoint(W.nt, wav, resid, grad)
+    torch.cuda.synchronize()
+    t_grad = (_t.perf_counter() - t0) / 3
+    misfit = 0.5 * float((resid.double() ** 2).sum())
+    s.close()
+    bytes_per_pt_step = 60  # forward with checkpoints 16 + recompute 16 + adjoint step 28
+    return {"workload": f"{W.name}, {W.nt} steps, two-layer model, smoothed start, 256x256 receivers, "
+                        f"checkpoint every {int(np.ceil(np.sqrt(W.nt)))} steps",
+            "forward_s": round(t_fwd, 4), "gradient_s": round(t_grad, 4), "ratio": round(t_grad / t_fwd, 3),
+            "gradient_gpts_per_s": round(W.npts * W.nt / t_grad / 1e9, 2),
+            "gradient_gb_per_s": round(bytes_per_pt_step * W.npts * W.nt / t_grad / 1e9, 1),
+            "misfit": misfit, "grad_finite": bool(torch.isfinite(grad).all().item())}
 
 
 def serving_leg(count: int) -> dict:
@@ -92,6 +232,8 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--nt", type=int, default=0, help="time steps per shot (default: the workload's 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the 16-bit, 1024^3 and gradient measurements")
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the Poisson shot stream to serve after the throughput run (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -161,6 +303,8 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] copy calibration: 3 x {src.numel() * 4} bytes read and written", file=sys.stderr,
               flush=True)
+        del src, dst
+    ceiling = stream_ceiling(dev, W.npts)
 
     out = {
         "metric": "stencil Gpts/s & % HBM roofline (1 GPU); shots/s with p50/p99 latency",
@@ -184,7 +328,15 @@ def main():
                      "kernel": "step_kernel", "kernel_ms": round(kernel_ms, 4),
                      "algorithmic_bytes_per_launch": bpp * W.npts},
         "nonfinite": bool(flags),
+        "stream_ceiling": ceiling,
     }
+    if not args.no_forms:
+        v_dev = torch.from_numpy(vel).to(dev)
+        out["forms_512"] = storage_forms_leg(W, v_dev, min(nt, 200))
+        del v_dev
+        out["precision_1024"] = precision_leg()
+        out["gradient_256"] = gradient_leg()
+        print(f"[bench] gradient: {out['gradient_256']}", file=sys.stderr, flush=True)
     if args.serving > 0:
         out["serving"] = serving_leg(args.serving)
     if not args.no_cpu_baseline:

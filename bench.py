@@ -26,7 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
-BYTES_PER_POINT = {"f32": 16, "f16": 10, "bf16": 10}
+# algorithmic bytes per point-step: float32 reads A^n, A^{n-1}, m and writes A^{n+1};
+# 16-bit storage reads A^n, V^n (2 B each) and m, writes A^{n+1} and V^{n+1}
+BYTES_PER_POINT = {"f32": 16, "f16": 12, "bf16": 12}
 
 
 def kernel_source_hash() -> str:

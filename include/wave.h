@@ -55,10 +55,14 @@ enum wave_status {
   WAVE_ESTATE = -5      /* call not valid for this context (e.g. no adjoint workspace) */
 };
 
+/* Float32 storage keeps (A^n, A^{n-1}).  16-bit storage keeps A^n and
+ * V^n = A^n - g A^{n-1} (so the step-to-step change is rounded relative to its
+ * own size), each with its own power-of-two scale, updated as
+ * V^{n+1} = g (V^n + m L(A^n) + q^n), A^{n+1} = g A^n + V^{n+1} in float32. */
 enum wave_storage {
   WAVE_F32 = 0,   /* float32 wavefields */
-  WAVE_F16 = 1,   /* IEEE half wavefields with a power-of-two scale per field, float32 arithmetic */
-  WAVE_BF16 = 2   /* bfloat16 wavefields, same scaling, float32 arithmetic */
+  WAVE_F16 = 1,   /* IEEE half A and V with a power-of-two scale per field, float32 arithmetic */
+  WAVE_BF16 = 2   /* bfloat16 A and V, same scaling, float32 arithmetic */
 };
 
 /* Flags reported by wave_sync_status. */
@@ -121,7 +125,8 @@ int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *re
                  float *grad_vel_dev);
 
 /* Copy a wavefield, decoded to float32, into out_dev [nz][ny][nx]:
- * which = 0: A^n, which = 1: A^{n-1} (undamped). */
+ * which = 0: A^n; which = 1: A^{n-1} (undamped); which = 2 (16-bit storage
+ * only, WAVE_EINVAL otherwise): the stored V^n = A^n - g A^{n-1}. */
 int wave_read_field(wave_t w, int32_t which, float *out_dev);
 
 /* Host copy of the step counter n. */

@@ -14,12 +14,14 @@ constexpr int kTileX = 64;   // tile width in x: one wavefront row
 struct StepState {
   int32_t n;            // absolute index of the next step (advanced by bump kernels)
   int32_t pad0[3];
-  uint32_t amax[4];     // slot k%4: max |stored raw value| of field A^k (float bits)
-  int32_t exps[4];      // slot k%4: scale exponent e_k of field A^k (stored = A * 2^e)
+  uint32_t amax[4];     // 16-bit storage, slot k%4: max |stored raw value| of A^k (float bits)
+  int32_t exps[4];      // slot k%4: scale exponent of A^k (stored = A * 2^e)
   uint32_t flags;       // WAVE_FLAG_* bits
   uint32_t vmin_bits;   // velocity range from the create pass (float bits)
   uint32_t vmax_bits;
-  uint32_t pad1[17];
+  uint32_t amax_v[4];   // the same two records for V^k = A^k - g A^{k-1}
+  int32_t exps_v[4];
+  uint32_t pad1[9];
 };
 static_assert(sizeof(StepState) == 128, "state block layout");
 
@@ -41,10 +43,14 @@ struct RecBox {
 
 enum Storage { kF32 = 0, kF16 = 1, kBF16 = 2 };
 
+// Float32 storage keeps (A^n, A^{n-1}) and writes A^{n+1} over A^{n-1}.
+// 16-bit storage keeps (A^n, V^n = A^n - g A^{n-1}): `prev` and `vout` both
+// point at V (updated in place) and A^{n+1} goes to `out`.
 struct StepArgs {
   const void *cur;    // A^n (storage type)
-  const void *prev;   // A^{n-1}
-  void *out;          // A^{n+1}; may alias prev
+  const void *prev;   // A^{n-1} (float32) or V^n (16-bit)
+  void *out;          // A^{n+1}; may alias prev (float32)
+  void *vout;         // 16-bit storage: V^{n+1} (same buffer as prev)
   const float *m;     // (v dt)^2
   const float *gx, *gy, *gz;
   int nx, ny, nz;
@@ -58,7 +64,7 @@ struct StepArgs {
   int nrec;
   StepState *st;
   int k;              // this launch advances step st->n + k
-  float beta;         // 16-bit storage: growth bound of one step
+  float gamma;        // 16-bit storage: |m L A| <= gamma max|A| at every node
   // adjoint mode only
   const float *fwd;   // forward field A^k for the imaging term
   float *img;         // accumulator sum_k mu^{k+1} L(A^k)
@@ -74,13 +80,18 @@ struct Variant {
 
 int variant_count();
 Variant variant_info(int v);
+// Workgroups of the forward step kernel that fit on one CU at once.
+int step_blocks_per_cu(int storage, int variant);
 
 // Launchers; each returns the hipError_t of the launch.
 hipError_t launch_step(int storage, int variant, bool adjoint, const StepArgs &a, hipStream_t s);
 hipError_t launch_init_m(const float *vel, float *m, size_t n, float dt, StepState *st, hipStream_t s);
 hipError_t launch_bump(StepState *st, int count, hipStream_t s);
 hipError_t launch_decode(int storage, const void *field, float *out, size_t n, const StepState *st,
-                         int slot_from_n_offset, hipStream_t s);
+                         int slot_from_n_offset, bool v_field, hipStream_t s);
+hipError_t launch_decode_prev(int storage, const void *a, const void *v, float *out, const float *gx,
+                              const float *gy, const float *gz, int nx, int ny, int nz, const StepState *st,
+                              hipStream_t s);
 hipError_t launch_gather(int storage, const void *field, const int64_t *rec_lin, int nrec, float *traces,
                          const StepState *st, int k, hipStream_t s);
 hipError_t launch_scatter(float *field, const int64_t *rec_lin, int nrec, const float *m, const float *grec,

@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   constexpr int DUMMY = LH * LW;
   __shared__ float lds[2][LP];
   __shared__ float ldsF[ADJ ? 2 : 1][ADJ ? LP : 1];
-  __shared__ float red[BY];
+  __shared__ float red[BY], redv[BY];
 
   // XCD-aware tile order: hardware id b runs on XCD b % 8.
   const int nwg = static_cast<int>(gridDim.x);
@@ -188,22 +188,29 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   const bool xin = x < nx;
   const int yb = y0 + w * RY;  // first row of this wavefront
 
-  // ---- step index and 16-bit field scales
+  // ---- step index and 16-bit field scales.  16-bit storage: the exponents of
+  // A^{n+1} and V^{n+1} come from bounds valid at every node,
+  //   |V^{n+1}| <= max|V^n| + gamma max|A^n| + |q^n| = bV,  |A^{n+1}| <= max|A^n| + bV,
+  // so each is fixed before anything is written.
   const int n = ADJ ? 0 : a.st->n + a.k;
-  float inv_cur = 1.f, inv_prev = 1.f, s_next = 1.f, inv_next = 1.f;
+  float inv_cur = 1.f, inv_prev = 1.f, s_next = 1.f, inv_next = 1.f, sv_next = 1.f;
   if (S != kF32) {
-    const int ec = a.st->exps[n & 3], ep = a.st->exps[(n + 3) & 3];
-    inv_cur = exp2i(-ec);
-    inv_prev = exp2i(-ep);
-    const float acur = __uint_as_float(a.st->amax[n & 3]) * inv_cur;
-    const float aprev = __uint_as_float(a.st->amax[(n + 3) & 3]) * inv_prev;
+    const int ea = a.st->exps[n & 3], ev = a.st->exps_v[n & 3];
+    inv_cur = exp2i(-ea);
+    inv_prev = exp2i(-ev);
+    const float a_a = __uint_as_float(a.st->amax[n & 3]) * inv_cur;
+    const float a_v = __uint_as_float(a.st->amax_v[n & 3]) * inv_prev;
     const float qmag = a.sx >= 0 ? fabsf(a.wavelet[n]) * a.src_scale : 0.f;
-    const int e_next = scale_exponent(a.beta * acur + aprev + qmag);
-    s_next = exp2i(e_next);
-    inv_next = exp2i(-e_next);
+    const float bv = a_v + a.gamma * a_a + qmag;
+    const int ea_next = scale_exponent(a_a + bv), ev_next = scale_exponent(bv);
+    s_next = exp2i(ea_next);
+    inv_next = exp2i(-ea_next);
+    sv_next = exp2i(ev_next);
     if (logical == 0 && threadIdx.x == 0) {
-      a.st->exps[(n + 1) & 3] = e_next;
+      a.st->exps[(n + 1) & 3] = ea_next;
+      a.st->exps_v[(n + 1) & 3] = ev_next;
       a.st->amax[(n + 2) & 3] = 0u;
+      a.st->amax_v[(n + 2) & 3] = 0u;
     }
   }
 
@@ -354,7 +361,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
     if (zb + s < ze) load_stage(stg[s], zb + s);
 
   const float wsrc = (!ADJ && a.sx >= 0) ? a.wavelet[n] * a.src_scale : 0.f;
-  float amax_loc = 0.f;
+  float amax_loc = 0.f, amaxv_loc = 0.f;
 
   for (int zs = zb; zs < ze; zs += kQ) {
     // nine planes per trip with compile-time queue slots and stage indices, so
@@ -405,6 +412,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
 
       const size_t zc = static_cast<size_t>(z) * plane;
       const rsrc_t ro = make_rsrc(O + zc, pbytes);
+      const rsrc_t rvo = make_rsrc((S != kF32 ? static_cast<raw *>(a.vout) : O) + zc, pbytes);
       const int rzi = rec_plane(z);
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
@@ -424,15 +432,28 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
         const int ridx = at_rec ? (rzi * a.box.cny + ryi[j]) * a.box.cnx + rxi : 0;
         if (ADJ && at_rec) lap += rc[j];
         const float g = gxv * (gyv[j] * gzv);
-        float v = fmaf(-g, pc[j], 2.f * c);
-        v = fmaf(mc[j], lap, v);
-        if (!ADJ && srcj == j && z == a.sz) v += wsrc;
-        v *= g;
+        float v, vv = 0.f;
+        if (S == kF32) {  // A^{n+1} = g (2 A^n - g A^{n-1} + m L A^n + q)
+          v = fmaf(-g, pc[j], 2.f * c);
+          v = fmaf(mc[j], lap, v);
+          if (!ADJ && srcj == j && z == a.sz) v += wsrc;
+          v *= g;
+        } else {  // V^{n+1} = g (V^n + m L A^n + q),  A^{n+1} = g A^n + V^{n+1}
+          vv = fmaf(mc[j], lap, pc[j]);
+          if (srcj == j && z == a.sz) vv += wsrc;
+          vv *= g;
+          v = fmaf(g, c, vv);
+        }
         if (ok[j] && live) {
           const raw r = C::enc(v * s_next);
           B::template st<kNT>(r, ro, vo, rowo[j]);
           const float stored = C::dec(r);
-          if (S != kF32) amax_loc = fmaxf(amax_loc, fabsf(stored));
+          if (S != kF32) {
+            const raw rv = C::enc(vv * sv_next);
+            B::template st<kNT>(rv, rvo, vo, rowo[j]);
+            amax_loc = fmaxf(amax_loc, fabsf(stored));
+            amaxv_loc = fmaxf(amaxv_loc, fabsf(C::dec(rv)));
+          }
           if (!ADJ && at_rec) a.traces[static_cast<size_t>(n) * a.nrec + ridx] = stored * inv_next;
           if (ADJ) {
             const float *rowF = LF + (R + w * RY + j) * LW + R + lane;
@@ -454,16 +475,26 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
     });
   }
 
-  if (S != kF32) {  // one order-independent atomic per workgroup
+  if (S != kF32) {  // one order-independent atomic per workgroup and field
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) amax_loc = fmaxf(amax_loc, __shfl_xor(amax_loc, off, 64));
-    if (lane == 0) red[w] = amax_loc;
+    for (int off = 32; off > 0; off >>= 1) {
+      amax_loc = fmaxf(amax_loc, __shfl_xor(amax_loc, off, 64));
+      amaxv_loc = fmaxf(amaxv_loc, __shfl_xor(amaxv_loc, off, 64));
+    }
+    if (lane == 0) {
+      red[w] = amax_loc;
+      redv[w] = amaxv_loc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      float mx = red[0];
+      float mx = red[0], mv = redv[0];
 #pragma unroll
-      for (int k = 1; k < BY; ++k) mx = fmaxf(mx, red[k]);
+      for (int k = 1; k < BY; ++k) {
+        mx = fmaxf(mx, red[k]);
+        mv = fmaxf(mv, redv[k]);
+      }
       atomicMax(&a.st->amax[(n + 1) & 3], __float_as_uint(mx));
+      atomicMax(&a.st->amax_v[(n + 1) & 3], __float_as_uint(mv));
     }
   }
 }
@@ -526,17 +557,39 @@ __global__ void reset_state_kernel(StepState *st) {
   if (t < 4) {
     st->amax[t] = 0u;
     st->exps[t] = 0;
+    st->amax_v[t] = 0u;
+    st->exps_v[t] = 0;
   }
 }
 
 template <int S>
 __global__ void decode_kernel(const typename Codec<S>::raw *__restrict__ f, float *__restrict__ out, size_t n,
-                              const StepState *st, int slot_off) {
-  const int e = S == kF32 ? 0 : st->exps[(st->n + slot_off) & 3];
+                              const StepState *st, int slot_off, int v_field) {
+  const int slot = (st->n + slot_off) & 3;
+  const int e = S == kF32 ? 0 : (v_field ? st->exps_v[slot] : st->exps[slot]);
   const float inv = exp2i(-e);
   for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<size_t>(gridDim.x) * blockDim.x)
     out[i] = Codec<S>::dec(f[i]) * inv;
+}
+
+// A^{n-1} = (A^n - V^n) / g from the 16-bit velocity-form pair.
+template <int S>
+__global__ void decode_prev_kernel(const typename Codec<S>::raw *__restrict__ fa,
+                                   const typename Codec<S>::raw *__restrict__ fv, float *__restrict__ out,
+                                   const float *__restrict__ gx, const float *__restrict__ gy,
+                                   const float *__restrict__ gz, int nx, int ny, int nz, const StepState *st) {
+  const int slot = st->n & 3;
+  const float ia = exp2i(-st->exps[slot]), iv = exp2i(-st->exps_v[slot]);
+  const size_t total = static_cast<size_t>(nx) * ny * nz;
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int x = static_cast<int>(i % nx);
+    const int y = static_cast<int>((i / nx) % ny);
+    const int z = static_cast<int>(i / (static_cast<size_t>(nx) * ny));
+    const float g = gx[x] * (gy[y] * gz[z]);
+    out[i] = (Codec<S>::dec(fa[i]) * ia - Codec<S>::dec(fv[i]) * iv) / g;
+  }
 }
 
 template <int S>
@@ -595,6 +648,30 @@ constexpr Variant kVariants[] = {{8, 4, 3}, {4, 8, 1}, {4, 4, 3}, {8, 2, 3},
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 template <int S, int BY, int RY, int PD, bool ADJ>
+int blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(step_kernel<S, BY, RY, PD, ADJ>),
+                                                   64 * BY, 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+template <int S, bool ADJ>
+int blocks_variant(int v) {
+  switch (v) {
+    case 0: return blocks_per_cu<S, 8, 4, 3, ADJ>();
+    case 1: return blocks_per_cu<S, 4, 8, 1, ADJ>();
+    case 2: return blocks_per_cu<S, 4, 4, 3, ADJ>();
+    case 3: return blocks_per_cu<S, 8, 2, 3, ADJ>();
+    case 4: return blocks_per_cu<S, 4, 4, 1, ADJ>();
+    case 5: return blocks_per_cu<S, 8, 4, 1, ADJ>();
+    case 6: return blocks_per_cu<S, 2, 8, 1, ADJ>();
+    case 7: return blocks_per_cu<S, 4, 2, 3, ADJ>();
+    default: return 1;
+  }
+}
+
+template <int S, int BY, int RY, int PD, bool ADJ>
 hipError_t launch_one(const StepArgs &a, hipStream_t s) {
   const unsigned grid = static_cast<unsigned>((a.total_tiles + 7) / 8 * 8);
   hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, ADJ>), dim3(grid), dim3(64 * BY), 0, s, a);
@@ -619,6 +696,16 @@ hipError_t launch_variant(int v, const StepArgs &a, hipStream_t s) {
 }  // namespace
 
 int variant_count() { return kNumVariants; }
+
+int step_blocks_per_cu(int storage, int variant) {
+  if (variant < 0 || variant >= kNumVariants) return 1;
+  switch (storage) {
+    case kF32: return blocks_variant<kF32, false>(variant);
+    case kF16: return blocks_variant<kF16, false>(variant);
+    case kBF16: return blocks_variant<kBF16, false>(variant);
+    default: return 1;
+  }
+}
 
 Variant variant_info(int v) { return kVariants[v]; }
 
@@ -657,12 +744,32 @@ hipError_t launch_reset_state(StepState *st, hipStream_t s) {
 }
 
 hipError_t launch_decode(int storage, const void *field, float *out, size_t n, const StepState *st,
-                         int slot_off, hipStream_t s) {
+                         int slot_off, bool v_field, hipStream_t s) {
+  const dim3 g(grid_for(n, 256)), b(256);
+  const int vf = v_field ? 1 : 0;
+  switch (storage) {
+    case kF32: hipLaunchKernelGGL(decode_kernel<kF32>, g, b, 0, s, (const float *)field, out, n, st, slot_off, vf); break;
+    case kF16: hipLaunchKernelGGL(decode_kernel<kF16>, g, b, 0, s, (const uint16_t *)field, out, n, st, slot_off, vf); break;
+    case kBF16: hipLaunchKernelGGL(decode_kernel<kBF16>, g, b, 0, s, (const uint16_t *)field, out, n, st, slot_off, vf); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_prev(int storage, const void *fa, const void *fv, float *out, const float *gx,
+                              const float *gy, const float *gz, int nx, int ny, int nz, const StepState *st,
+                              hipStream_t s) {
+  const size_t n = static_cast<size_t>(nx) * ny * nz;
   const dim3 g(grid_for(n, 256)), b(256);
   switch (storage) {
-    case kF32: hipLaunchKernelGGL(decode_kernel<kF32>, g, b, 0, s, (const float *)field, out, n, st, slot_off); break;
-    case kF16: hipLaunchKernelGGL(decode_kernel<kF16>, g, b, 0, s, (const uint16_t *)field, out, n, st, slot_off); break;
-    case kBF16: hipLaunchKernelGGL(decode_kernel<kBF16>, g, b, 0, s, (const uint16_t *)field, out, n, st, slot_off); break;
+    case kF16:
+      hipLaunchKernelGGL(decode_prev_kernel<kF16>, g, b, 0, s, (const uint16_t *)fa, (const uint16_t *)fv, out, gx,
+                         gy, gz, nx, ny, nz, st);
+      break;
+    case kBF16:
+      hipLaunchKernelGGL(decode_prev_kernel<kBF16>, g, b, 0, s, (const uint16_t *)fa, (const uint16_t *)fv, out,
+                         gx, gy, gz, nx, ny, nz, st);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -23,7 +23,7 @@ constexpr double kC[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct Layout {
-  size_t st, gx, gy, gz, rec_lin, grec, m, fa, fb, ckpt, seg, mua, mub, img, total;
+  size_t st, gx, gy, gz, rec_lin, grec, m, fa, fb, fv, ckpt, seg, mua, mub, img, total;
   int K, nck;
 };
 
@@ -74,6 +74,8 @@ int plan(const wave_params *p, Layout *L) {
   L->m = take(4 * N);
   L->fa = take(es * N);
   L->fb = take(es * N);
+  // 16-bit storage keeps V^n = A^n - g A^{n-1} besides the A ping-pong pair
+  L->fv = p->storage == WAVE_F32 ? off : take(es * N);
   L->K = 0;
   L->nck = 0;
   L->ckpt = L->seg = L->mua = L->mub = L->img = off;
@@ -143,11 +145,11 @@ struct wave_ctx {
   StepState *st = nullptr;
   float *gx = nullptr, *gy = nullptr, *gz = nullptr, *m = nullptr, *grec = nullptr;
   int64_t *rec_lin = nullptr;
-  void *fa = nullptr, *fb = nullptr;
+  void *fa = nullptr, *fb = nullptr, *fv = nullptr;
   size_t N = 0;
   int n = 0;  // host mirror of the step counter
   Coef c{};
-  float src_scale = 0.f, beta = 2.f;
+  float src_scale = 0.f, gamma = 0.f;
   RecBox box{};
   bool fused_rec = false;
   int tiles_x = 0, tiles_y = 0, nchunks = 0, zchunk = 0, total_tiles = 0;
@@ -191,7 +193,7 @@ StepArgs base_args(const wave_ctx *w) {
   a.sz = w->p.src[2];
   a.src_scale = w->src_scale;
   a.st = w->st;
-  a.beta = w->beta;
+  a.gamma = w->gamma;
   a.nrec = w->p.nrec;
   return a;
 }
@@ -206,8 +208,9 @@ int enqueue_steps(wave_ctx *w, int count, const float *wavelet, float *traces, b
   for (int k = 0; k < count; ++k) {
     const int parity = (w->n + k) & 1;
     a.cur = w->field(parity);
-    a.prev = w->field(parity ^ 1);
     a.out = w->field(parity ^ 1);
+    a.prev = w->p.storage == WAVE_F32 ? w->field(parity ^ 1) : w->fv;
+    a.vout = w->fv;
     a.k = k;
     int rc = hip_rc(launch_step(w->p.storage, w->p.variant, false, a, w->stream));
     if (rc) return rc;
@@ -278,6 +281,7 @@ int do_reset(wave_ctx *w) {
   const size_t es = w->p.storage == WAVE_F32 ? 4 : 2;
   int rc = hip_rc(launch_fill_zero(w->fa, es * w->N, w->stream));
   if (!rc) rc = hip_rc(launch_fill_zero(w->fb, es * w->N, w->stream));
+  if (!rc && w->fv) rc = hip_rc(launch_fill_zero(w->fv, es * w->N, w->stream));
   if (!rc) rc = hip_rc(launch_reset_state(w->st, w->stream));
   if (!rc) w->n = 0;
   return rc;
@@ -333,6 +337,7 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   w->m = reinterpret_cast<float *>(w->ws + L.m);
   w->fa = w->ws + L.fa;
   w->fb = w->ws + L.fb;
+  w->fv = p->storage == WAVE_F32 ? nullptr : w->ws + L.fv;
   const int nx = p->nx, ny = p->ny, nz = p->nz;
   w->N = static_cast<size_t>(nx) * ny * nz;
 
@@ -358,17 +363,20 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   w->fused_rec = detect_box(w->rec, p->nrec, &w->box);
   if (!w->fused_rec) w->box = RecBox{};
 
-  // tiling
-  const Variant v = variant_info(p->variant);
+  // tiling.  variant 0 selects the measured-best shape per storage type: 8
+  // wavefronts x 4 rows for float32, 8 x 2 rows for 16-bit storage (variant 3),
+  // whose lower register count fits two workgroups per CU.
+  if (p->variant == 0 && p->storage != WAVE_F32) w->p.variant = 3;
+  const Variant v = variant_info(w->p.variant);
   const int TY = v.by * v.ry;
   w->tiles_x = (nx + kTileX - 1) / kTileX;
   w->tiles_y = (ny + TY - 1) / TY;
   int zc = p->zchunk;
   if (zc <= 0) {
-    // about one long-lived workgroup per CU (256 CUs): long z-chunks re-read
-    // fewer overlap planes and keep the prefetch pipeline full
+    // as many long-lived workgroups as fit on the 256 CUs at once: long
+    // z-chunks re-read fewer overlap planes and keep the prefetch pipeline full
     const int per_plane = w->tiles_x * w->tiles_y;
-    const int want = 256;
+    const int want = 256 * step_blocks_per_cu(p->storage, w->p.variant);
     const int chunks = std::max(1, (want + per_plane / 2) / per_plane);
     zc = std::max(18, (nz + chunks - 1) / chunks);
     zc = (zc + 8) / 9 * 9;  // the kernel advances nine planes per trip
@@ -399,12 +407,11 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
     const double peak = 2048.0 / 315.0;  // max |symbol| of the 1D stencil, at the Nyquist wavenumber
     const double Mmax = static_cast<double>(vmax) * p->dt * static_cast<double>(vmax) * p->dt;
     if (Mmax * peak * (ix2 + iy2 + iz2) > 4.0 * (1.0 + 1e-12)) rc = WAVE_EUNSTABLE;
-    // growth bound of one step for the 16-bit scale:
-    // |2A + M L A| <= (|2 + M k0| + M sum |k|) max|A|
+    // 16-bit scale bound: |M L A| <= Mmax (|k0| + sum_{a,m} 2 |c_m| / h_a^2) max|A|
     double kabs = 0.0;
     for (int m = 1; m <= 4; ++m) kabs += 2.0 * std::fabs(kC[m]) * (ix2 + iy2 + iz2);
     const double k0 = kC[0] * (ix2 + iy2 + iz2);
-    w->beta = static_cast<float>(std::max(2.0, std::fabs(2.0 + Mmax * k0) + Mmax * kabs));
+    w->gamma = static_cast<float>(Mmax * (std::fabs(k0) + kabs));
   }
   if (!rc) rc = do_reset(w);
   if (rc) {
@@ -513,9 +520,18 @@ int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *re
 }
 
 int wave_read_field(wave_t w, int32_t which, float *out_dev) {
-  if (!w || !out_dev || (which != 0 && which != 1)) return WAVE_EINVAL;
-  const void *f = w->field((w->n & 1) ^ which);
-  return hip_rc(launch_decode(w->p.storage, f, out_dev, w->N, w->st, which ? 3 : 0, w->stream));
+  if (!w || !out_dev || which < 0 || which > 2) return WAVE_EINVAL;
+  const bool f32 = w->p.storage == WAVE_F32;
+  if (which == 0)
+    return hip_rc(launch_decode(w->p.storage, w->field(w->n & 1), out_dev, w->N, w->st, 0, false, w->stream));
+  if (which == 2) {
+    if (f32) return WAVE_EINVAL;
+    return hip_rc(launch_decode(w->p.storage, w->fv, out_dev, w->N, w->st, 0, true, w->stream));
+  }
+  if (f32)
+    return hip_rc(launch_decode(w->p.storage, w->field((w->n & 1) ^ 1), out_dev, w->N, w->st, 3, false, w->stream));
+  return hip_rc(launch_decode_prev(w->p.storage, w->field(w->n & 1), w->fv, out_dev, w->gx, w->gy, w->gz, w->p.nx,
+                                   w->p.ny, w->p.nz, w->st, w->stream));
 }
 
 int wave_time_index(wave_t w, int32_t *n) {

@@ -86,41 +86,61 @@ typedef struct {
   int32_t graph_steps;       /* >0: replay steps from a captured HIP graph of this many steps */
 } wave_params;
 
-/* Fill `p` with defaults: no source, no receivers, float32, alpha 0.015. */
+/* Fill `p` with defaults: no source, no receivers, float32 storage,
+ * alpha 0.015, unit spacings and dt (callers set the grid and dt). */
 void wave_params_init(wave_params *p);
 
-/* Bytes of device workspace wave_create needs for `p` (256-byte aligned). */
+/* Bytes of device workspace wave_create needs for `p`: m = (v dt)^2, the
+ * wavefields of the update (two float32 fields, or three 16-bit fields A,
+ * A', V), the sponge tables, the receiver map and, with adjoint != 0, the
+ * checkpoints, the recomputation buffer and the adjoint fields.  Validates `p`
+ * (WAVE_EINVAL on any bad field); touches no device. */
 int wave_workspace_bytes(const wave_params *p, size_t *bytes);
 
-/* Create a context.  vel_dev: device float32 [nz][ny][nx] velocity (m/s),
- * finite and > 0, read during the call only (m = (v dt)^2 is stored in the
- * workspace).  ws_dev: device workspace of ws_bytes >= wave_workspace_bytes,
- * 256-byte aligned.  hip_stream: the hipStream_t all work is queued on
- * (NULL = default stream).  Synchronises that stream once.  The state is
- * reset: A^0 = A^{-1} = 0, n = 0. */
+/* Create a context: the setup of the update of paper Sec. II (Eq. 1 weights
+ * divided by h_a^2, m = (v dt)^2, sponge tables, receiver map).
+ * vel_dev: device float32 [nz][ny][nx] velocity (m/s), finite and > 0, read
+ * during the call only (m is stored in the workspace).  ws_dev: device
+ * workspace of ws_bytes >= wave_workspace_bytes, 256-byte aligned, owned by
+ * the caller and borrowed until wave_destroy.  hip_stream: the hipStream_t all
+ * work is queued on (NULL = default stream).  Synchronises that stream once to
+ * read back the velocity range.  Errors: WAVE_EINVAL (bad params, pointer,
+ * alignment, non-finite or non-positive velocity), WAVE_ENOSPC (workspace too
+ * small), WAVE_EUNSTABLE (max(v) dt above the leapfrog stability limit
+ * 2 / sqrt(2048/315 * sum_a h_a^-2)), WAVE_EHIP.  The state is reset:
+ * A^0 = A^{-1} = 0, n = 0. */
 int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t ws_bytes,
                 void *hip_stream, wave_t *out);
 
-/* Zero both wavefields and the step counter n. */
+/* Zero the wavefields and the step counter n (enqueued on the stream). */
 int wave_reset(wave_t w);
 
-/* Advance nsteps >= 0 steps from the current n.  wavelet_dev: device float32
- * s(t_k) indexed by the absolute step k since the last reset (entries
- * n..n+nsteps-1 are read; may be NULL without a source).  traces_dev: device
- * float32 [k][nrec], absolute rows n..n+nsteps-1 are written (may be NULL
- * when nrec == 0).  For 16-bit storage a trace holds the stored (rounded)
- * value. */
+/* Advance nsteps >= 0 steps from the current n: the per-iteration update of
+ * paper Sec. II (Eq. 1 at every node, once per time step), fused with the
+ * sponge, the source and the receivers as in the formula at the top.
+ * wavelet_dev: device float32 s(t_k) indexed by the absolute step k since the
+ * last reset (entries n..n+nsteps-1 are read; may be NULL without a source).
+ * traces_dev: device float32 [k][nrec], absolute rows n..n+nsteps-1 are written
+ * (may be NULL when nrec == 0); both arrays are the caller's and must stay
+ * valid until the stream reaches this work.  With graph_steps > 0 the steps
+ * are replayed from captured HIP graphs (bit-identical results).  For 16-bit
+ * storage a trace holds the stored (rounded) value.  Errors: WAVE_EINVAL
+ * (null context, nsteps < 0, a needed pointer NULL), WAVE_EHIP. */
 int wave_step(wave_t w, int32_t nsteps, const float *wavelet_dev, float *traces_dev);
 
-/* wave_reset followed by wave_step(nt). */
+/* wave_reset followed by wave_step(nt): one whole forward shot. */
 int wave_run(wave_t w, int32_t nt, const float *wavelet_dev, float *traces_dev);
 
-/* Velocity gradient of J = 1/2 sum_{n,r} resid-weighted misfit: given the
- * residual r^n = dJ/dtrace[n] (device float32 [nt][nrec]), writes
- * grad_vel_dev (device float32, N) = dJ/dv, by the exact discrete adjoint of
- * the step above with checkpointed recomputation of the forward field.
- * Requires adjoint != 0 at create, storage == WAVE_F32 and nt <= nt_max.
- * Leaves the context reset (n = 0). */
+/* Velocity gradient for subsurface imaging (the application of paper Sec. I;
+ * the paper has no adjoint): for any scalar J of the traces of an nt-step
+ * shot, given resid_dev = dJ/dtrace (device float32 [nt][nrec]), writes
+ * grad_vel_dev (device float32 [nz][ny][nx]) = dJ/dv.  Exact discrete adjoint
+ * of wave_step: a forward run storing (A^k, A^{k-1}) every ckpt_interval
+ * steps, then per segment, last first, a recomputation of the segment's
+ * forward fields and the backward adjoint steps with the imaging term fused
+ * (mu = m g lambda; dJ/dv = (2/v) sum_n mu^{n+1} L(A^n)).  Requires
+ * adjoint != 0 at create (else WAVE_ESTATE), storage == WAVE_F32 and
+ * 1 <= nt <= nt_max (else WAVE_EINVAL).  Leaves the context reset (n = 0). */
 int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *resid_dev,
                  float *grad_vel_dev);
 
@@ -129,10 +149,11 @@ int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *re
  * only, WAVE_EINVAL otherwise): the stored V^n = A^n - g A^{n-1}. */
 int wave_read_field(wave_t w, int32_t which, float *out_dev);
 
-/* Host copy of the step counter n. */
+/* Host copy of the step counter n (steps since the last reset). */
 int wave_time_index(wave_t w, int32_t *n);
 
-/* Synchronise the stream and report WAVE_FLAG_* bits for the current field. */
+/* Synchronise the stream and report WAVE_FLAG_* bits for the current field
+ * (WAVE_FLAG_NONFINITE: A^n holds an infinity or NaN). */
 int wave_sync_status(wave_t w, uint32_t *flags);
 
 /* Free the host context (the workspace stays the caller's). */

@@ -69,7 +69,7 @@ enum wave_storage {
 enum { WAVE_FLAG_NONFINITE = 1u };
 
 typedef struct {
-  int32_t nx, ny, nz;        /* grid nodes per axis, >= 1; nx*ny < 2^29 */
+  int32_t nx, ny, nz;        /* grid nodes per axis, >= 1; nx*ny <= 2^24 */
   double dx, dy, dz;         /* grid spacing (m), > 0 */
   double dt;                 /* time step (s), > 0, at most the stability limit */
   int32_t sponge_width;      /* damping strip width in nodes; 0 = zero-Dirichlet only */
@@ -81,8 +81,11 @@ typedef struct {
   int32_t adjoint;           /* nonzero: reserve the workspace wave_adjoint needs (float32 only) */
   int32_t nt_max;            /* adjoint: largest nt wave_adjoint will be called with */
   int32_t ckpt_interval;     /* adjoint: steps between checkpoints; 0 = ceil(sqrt(nt_max)) */
-  int32_t variant;           /* kernel tiling variant (0 = default; see wave_variant_count) */
-  int32_t zchunk;            /* z-planes per workgroup; 0 = chosen from the grid size */
+  int32_t variant;           /* kernel tile shape, 1 .. wave_variant_count()-1; 0 = automatic (the
+                                measured-best shape for the storage type and nx); shapes with 2 or 4
+                                x nodes per lane need nx divisible by 2 or 4 (else WAVE_EINVAL) */
+  int32_t zchunk;            /* z-planes per workgroup, rounded up to a multiple of 9 and capped so a
+                                workgroup's buffers span < 2 GiB; 0 = chosen from the grid size */
   int32_t graph_steps;       /* >0: replay steps from a captured HIP graph of this many steps */
 } wave_params;
 

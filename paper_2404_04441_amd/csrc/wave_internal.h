@@ -9,6 +9,11 @@ namespace wave {
 
 constexpr int kRadius = 4;   // stencil half-width (8th order)
 constexpr int kTileX = 64;   // tile width in x: one wavefront row
+constexpr int kMaxPD = 3;    // most z-planes of loads a step kernel keeps in flight
+// Zero planes after the nz interior planes of every field the step kernel
+// reads or writes: the last z-chunk's final nine-plane trip, its prefetches
+// and its z halo run into them instead of past the allocation.
+constexpr int kPadZ = 2 * kRadius + kMaxPD + kRadius;
 
 // Device-resident per-run state, at the head of the workspace.
 struct StepState {
@@ -53,6 +58,7 @@ struct StepArgs {
   void *vout;         // 16-bit storage: V^{n+1} (same buffer as prev)
   const float *m;     // (v dt)^2
   const float *gx, *gy, *gz;
+  const int *rz;       // per plane: receiver-box plane index, or -1
   int nx, ny, nz;
   int tiles_x, tiles_y, nchunks, zchunk, total_tiles;
   Coef c;
@@ -76,6 +82,7 @@ struct Variant {
   int by;   // wavefronts per workgroup
   int ry;   // consecutive rows per wavefront (tile height = by * ry)
   int pd;   // z-planes of loads in flight ahead of the plane being computed
+  int vec;  // consecutive x nodes per lane (tile width = 64 * vec); needs nx % vec == 0
 };
 
 int variant_count();

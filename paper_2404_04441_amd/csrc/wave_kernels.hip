@@ -92,6 +92,10 @@ template <typename T> __device__ __forceinline__ void st_stream(T v, T *p) { __b
 // array (rows, planes and columns are clamped), ghost values are selected
 // to zero where they are consumed.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
 constexpr int kNT = 2;                  // nontemporal cache policy bit
 
@@ -100,70 +104,159 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
                                            static_cast<int>(bytes), kRsrcWord3);
 }
 
-template <typename T> struct Buf;
-template <> struct Buf<float> {
-  template <int AUX> __device__ static float ld(rsrc_t r, uint32_t vo, uint32_t so) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(vo),
-                                                                          static_cast<int>(so), AUX));
-  }
-  template <int AUX> __device__ static void st(float v, rsrc_t r, uint32_t vo, uint32_t so) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, static_cast<int>(vo),
-                                          static_cast<int>(so), AUX);
-  }
-};
-template <> struct Buf<uint16_t> {
-  template <int AUX> __device__ static uint16_t ld(rsrc_t r, uint32_t vo, uint32_t so) {
-    return __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(vo), static_cast<int>(so), AUX);
-  }
-  template <int AUX> __device__ static void st(uint16_t v, rsrc_t r, uint32_t vo, uint32_t so) {
-    __builtin_amdgcn_raw_buffer_store_b16(v, r, static_cast<int>(vo), static_cast<int>(so), AUX);
-  }
+// ---- rows of VEC consecutive values as loaded: NB bytes in 32-bit words
+// (a 16-bit value alone is zero-extended into one word).
+template <int NB> struct Words {
+  static constexpr int N = (NB + 3) / 4;
+  uint32_t w[N];
 };
 
+template <int NB, int AUX>
+__device__ __forceinline__ Words<NB> ld_words(rsrc_t r, uint32_t vo, uint32_t so) {
+  Words<NB> out;
+  const int v = static_cast<int>(vo), s = static_cast<int>(so);
+  if constexpr (NB == 2) {
+    out.w[0] = __builtin_amdgcn_raw_buffer_load_b16(r, v, s, AUX);
+  } else if constexpr (NB == 4) {
+    out.w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, v, s, AUX);
+  } else if constexpr (NB == 8) {
+    const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(r, v, s, AUX);
+    out.w[0] = t.x;
+    out.w[1] = t.y;
+  } else {
+    static_assert(NB == 16, "row width");
+    const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(r, v, s, AUX);
+    out.w[0] = t.x;
+    out.w[1] = t.y;
+    out.w[2] = t.z;
+    out.w[3] = t.w;
+  }
+  return out;
+}
+
+template <int NB, int AUX>
+__device__ __forceinline__ void st_words(const Words<NB> &in, rsrc_t r, uint32_t vo, uint32_t so) {
+  const int v = static_cast<int>(vo), s = static_cast<int>(so);
+  if constexpr (NB == 2) {
+    __builtin_amdgcn_raw_buffer_store_b16(static_cast<uint16_t>(in.w[0]), r, v, s, AUX);
+  } else if constexpr (NB == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(in.w[0], r, v, s, AUX);
+  } else if constexpr (NB == 8) {
+    __builtin_amdgcn_raw_buffer_store_b64(u32x2{in.w[0], in.w[1]}, r, v, s, AUX);
+  } else {
+    static_assert(NB == 16, "row width");
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{in.w[0], in.w[1], in.w[2], in.w[3]}, r, v, s, AUX);
+  }
+}
+
+// Value i of a row of storage type S (decoded, unscaled) and the inverse.
+template <int S, int NB>
+__device__ __forceinline__ float row_get(const Words<NB> &r, int i) {
+  if constexpr (S == kF32) {
+    return __uint_as_float(r.w[i]);
+  } else {
+    const uint32_t h = (r.w[i >> 1] >> (16 * (i & 1))) & 0xffffu;
+    return Codec<S>::dec(static_cast<uint16_t>(h));
+  }
+}
+template <int S, int VEC>
+__device__ __forceinline__ Words<VEC * (S == kF32 ? 4 : 2)> row_put(const float *v) {
+  Words<VEC * (S == kF32 ? 4 : 2)> r;
+  if constexpr (S == kF32) {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) r.w[i] = __float_as_uint(v[i]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < r.N; ++k) r.w[k] = 0u;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) r.w[i >> 1] |= static_cast<uint32_t>(Codec<S>::enc(v[i])) << (16 * (i & 1));
+  }
+  return r;
+}
+
+// LDS rows of VEC floats at a VEC-aligned address.
+template <int VEC> __device__ __forceinline__ void lds_put(float *p, const float *v) {
+  if constexpr (VEC == 1) {
+    p[0] = v[0];
+  } else if constexpr (VEC == 2) {
+    *reinterpret_cast<f32x2 *>(p) = f32x2{v[0], v[1]};
+  } else {
+    *reinterpret_cast<f32x4 *>(p) = f32x4{v[0], v[1], v[2], v[3]};
+  }
+}
+template <int VEC> __device__ __forceinline__ void lds_get(const float *p, float *v) {
+  if constexpr (VEC == 1) {
+    v[0] = p[0];
+  } else if constexpr (VEC == 2) {
+    const f32x2 t = *reinterpret_cast<const f32x2 *>(p);
+    v[0] = t.x;
+    v[1] = t.y;
+  } else {
+    const f32x4 t = *reinterpret_cast<const f32x4 *>(p);
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+    v[3] = t.w;
+  }
+}
+
 // Registers one thread holds for one z-plane of the pipeline: raw loaded
-// values, so that nothing waits on a load until the plane is consumed.  Every
+// rows, so that nothing waits on a load until the plane is consumed.  Every
 // vector-memory load of the z loop lives here: s_waitcnt vmcnt retires loads
 // in issue order, so a load consumed in the same iteration would also wait for
 // every prefetch issued before it.
-template <typename raw, int RY, int NYH, bool ADJ>
+template <int S, int RY, int VEC, int NYH, bool ADJ>
 struct Stage {
-  raw lead[RY];                 // A^n at plane z+R (enters the z queue)
-  raw p[RY];                    // A^{n-1} at plane z
-  float m[RY];                  // m at plane z
-  raw yh[NYH];                  // y-halo rows of A^n at plane z owned by this wavefront
-  raw xh;                       // x-halo value of A^n at plane z (lanes < 8*RY)
-  float gz;                     // sponge factor of plane z
-  float leadF[ADJ ? RY : 1];    // adjoint: forward field, same roles
-  float res[ADJ ? RY : 1];      // adjoint: residual injected at receivers of plane z
-  float yhF[ADJ ? NYH : 1];
+  static constexpr int NA = VEC * (S == kF32 ? 4 : 2);  // bytes of one A-type row
+  static constexpr int NF = VEC * 4;                    // bytes of one float row
+  Words<NA> lead[RY];             // A^n at plane z+R (enters the z queue)
+  Words<NA> p[RY];                // A^{n-1} (or V^n) at plane z
+  Words<NF> m[RY];                // m at plane z
+  Words<NA> yh[NYH];              // y-halo rows of A^n at plane z owned by this wavefront
+  Words<S == kF32 ? 4 : 2> xh;    // x-halo value of A^n at plane z (lanes < 8*RY)
+  float gz;                       // sponge factor of plane z
+  int rz;                         // receiver-box plane index of plane z, or -1
+  Words<NF> leadF[ADJ ? RY : 1];  // adjoint: forward field, same roles
+  Words<NF> img[ADJ ? RY : 1];    // adjoint: imaging accumulator at plane z
+  Words<NF> yhF[ADJ ? NYH : 1];
   float xhF;
-  float img[ADJ ? RY : 1];      // adjoint: imaging accumulator at plane z
+  float res[ADJ ? RY : 1][ADJ ? VEC : 1];  // adjoint: residual injected at receivers of plane z
 };
 
 constexpr int kQ = 2 * R + 1;  // z-queue length (planes z-4 .. z+4)
 
-// BY wavefronts per workgroup, RY consecutive rows per wavefront (tile 64 x
-// BY*RY), PD planes of loads in flight ahead of the plane being computed
-// (PD divides 9: the z loop is unrolled 9 times so the queue rotates by
-// register renaming instead of copies).
-template <int S, int BY, int RY, int PD, bool ADJ>
+// Lane byte offset past the end of every buffer resource the step kernel
+// builds (each spans less than 2^31 bytes, and resource offset plus this
+// value stays below 2^32): a load at it returns zero, a store is dropped.
+constexpr uint32_t kOOB = 0x80000000u;
+static_assert(kPadZ >= (kQ - 1) + kMaxPD + R, "z padding must cover the last trip's loads");
+
+// BY wavefronts per workgroup, RY consecutive rows per wavefront, VEC
+// consecutive x nodes per lane (tile 64*VEC x BY*RY), PD planes of loads in
+// flight ahead of the plane being computed (PD divides 9: the z loop is
+// unrolled 9 times so the queue rotates by register renaming instead of
+// copies).  VEC > 1 requires nx % VEC == 0 (whole rows stay aligned).
+template <int S, int BY, int RY, int PD, int VEC, bool ADJ>
 __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   using C = Codec<S>;
-  using raw = typename C::raw;
-  using B = Buf<raw>;
+  using StageT = Stage<S, RY, VEC, (2 * R + BY - 1) / BY, ADJ>;
+  constexpr int NA = StageT::NA, NF = StageT::NF;
+  constexpr int TX = kTileX * VEC;
   constexpr int TY = BY * RY;
-  constexpr int LW = kTileX + 2 * R;
+  constexpr int LW = TX + 2 * R;
   constexpr int LH = TY + 2 * R;
   constexpr int NYH = (2 * R + BY - 1) / BY;
-  constexpr uint32_t ES = sizeof(raw);
+  constexpr uint32_t ES = S == kF32 ? 4u : 2u;
   static_assert(8 * RY <= 64, "x-halo of a wavefront's rows must fit in one load");
   static_assert(kQ % PD == 0, "pipeline depth must divide the queue length");
-  // each LDS plane ends with a 64-float scratch row: halo writes of lanes or
+  static_assert(PD <= kMaxPD, "z padding assumes at most kMaxPD planes in flight");
+  static_assert(VEC == 1 || VEC == 2 || VEC == 4, "lane width");
+  // each LDS plane ends with a scratch row: halo writes of lanes or
   // wavefronts with nothing to write go there, so no write is predicated
-  constexpr int LP = LH * LW + 64;
+  constexpr int LP = LH * LW + 64 * VEC;
   constexpr int DUMMY = LH * LW;
-  __shared__ float lds[2][LP];
-  __shared__ float ldsF[ADJ ? 2 : 1][ADJ ? LP : 1];
+  __shared__ __attribute__((aligned(16))) float lds[2][LP];
+  __shared__ __attribute__((aligned(16))) float ldsF[ADJ ? 2 : 1][ADJ ? LP : 1];
   __shared__ float red[BY], redv[BY];
 
   // XCD-aware tile order: hardware id b runs on XCD b % 8.
@@ -175,18 +268,21 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   const int rest = logical / a.tiles_x;
   const int tiy = rest % a.tiles_y;
   const int chunk = rest / a.tiles_y;
-  const int x0 = tix * kTileX, y0 = tiy * TY;
+  const int x0 = tix * TX, y0 = tiy * TY;
+  // planes [zb, ze) of this chunk, nine per trip: the last chunk's final
+  // trip runs on into the zero padding planes past nz (sponge factor 0, so
+  // they are written with zeros and stay zero)
   const int zb = chunk * a.zchunk;
-  const int ze = min(zb + a.zchunk, a.nz);
+  const int ze = zb + (min(a.zchunk, a.nz - zb) + kQ - 1) / kQ * kQ;
   const int lane = static_cast<int>(threadIdx.x) & 63;
   const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int nx = a.nx, ny = a.ny;
   const size_t plane = static_cast<size_t>(nx) * static_cast<size_t>(ny);
   const uint32_t pbytes = static_cast<uint32_t>(plane) * ES;
   const uint32_t pbytes_f = static_cast<uint32_t>(plane) * 4u;
-  const int x = x0 + lane;
-  const bool xin = x < nx;
-  const int yb = y0 + w * RY;  // first row of this wavefront
+  const int x = x0 + VEC * lane;  // first of this lane's VEC columns
+  const bool xin = x < nx;        // all VEC columns (nx % VEC == 0)
+  const int yb = y0 + w * RY;     // first row of this wavefront
 
   // ---- step index and 16-bit field scales.  16-bit storage: the exponents of
   // A^{n+1} and V^{n+1} come from bounds valid at every node,
@@ -214,70 +310,93 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
     }
   }
 
-  // ---- per-row data (wavefront-uniform) and per-lane data
-  bool rowin[RY], ok[RY];
-  float gyv[RY];
-  int ryi[RY];
-  uint32_t rowo[RY], rowo_f[RY];  // byte offset of the (clamped) row in a plane
-  const uint32_t xl = static_cast<uint32_t>(min(x, nx - 1));
-  const float gxv = xin ? a.gx[x] : 0.f;
-  int rxi = -1;
-  if (a.box.cnx > 0 && xin) {
-    const int d = x - a.box.x0;
-    if (d >= 0 && d % a.box.sx == 0 && d / a.box.sx < a.box.cnx) rxi = d / a.box.sx;
+  // ---- buffer resources: one per field for the whole workgroup, based at
+  // the first plane it touches (zlo) and spanning the planes [zlo, zhi) its
+  // trips, prefetches and halo cover (the host keeps every span below 2^31
+  // bytes; the fields carry kPadZ zero planes past nz).  The plane goes into
+  // the scalar offset; a lane's row and column go into its vector offset,
+  // which is kOOB for nodes outside the grid, so those lanes load zeros and
+  // store nothing.  Planes below 0 (prologue only) use rnull (no records):
+  // every load from it is zero.
+  const int zlo = max(zb - R, 0);
+  const int zhi = ze + PD + R;
+  const uint32_t span = static_cast<uint32_t>(zhi - zlo) * pbytes;
+  const uint32_t span_f = static_cast<uint32_t>(zhi - zlo) * pbytes_f;
+  const size_t base = static_cast<size_t>(zlo) * plane;
+  const size_t base_b = base * ES;
+  const char *U = static_cast<const char *>(a.cur);
+  const char *P = static_cast<const char *>(a.prev);
+  char *O = static_cast<char *>(a.out);
+  const rsrc_t rU = make_rsrc(U + base_b, span);
+  const rsrc_t rP = make_rsrc(P + base_b, span);
+  const rsrc_t rO = make_rsrc(O + base_b, span);
+  const rsrc_t rVo = make_rsrc((S != kF32 ? static_cast<char *>(a.vout) : O) + base_b, span);
+  const rsrc_t rM = make_rsrc(a.m + base, span_f);
+  const rsrc_t rnull = make_rsrc(a.gz, 0u);
+  const rsrc_t rF = make_rsrc((ADJ ? a.fwd : a.m) + base, span_f);
+  const rsrc_t rI = make_rsrc((ADJ ? a.img : a.m) + base, ADJ ? span_f : 0u);
+  auto so = [&](int z) { return static_cast<uint32_t>(z - zlo) * pbytes; };     // plane offset, A fields
+  auto so_f = [&](int z) { return static_cast<uint32_t>(z - zlo) * pbytes_f; };  // plane offset, float fields
+
+  // ---- per-row data (wavefront-uniform) and per-lane offsets
+  float gxv[VEC], gyv[RY], qrow[RY];
+  int ryi[RY], rxi[VEC];
+  uint32_t vrow[RY], vrow_f[RY];  // lane byte offset of (x, row j) in a plane, or kOOB
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) {
+    gxv[i] = xin ? a.gx[x + i] : 0.f;
+    rxi[i] = -1;
+    if (a.box.cnx > 0 && xin) {
+      const int d = x + i - a.box.x0;
+      if (d >= 0 && d % a.box.sx == 0 && d / a.box.sx < a.box.cnx) rxi[i] = d / a.box.sx;
+    }
   }
-  int srcj = -1;
+  // the source node: qrow[j] = 1 in its lane and row, its column index srci
+  const int srci = (!ADJ && a.sx >= 0) ? (a.sx - x0) % VEC : 0;
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
     const int yj = yb + j;
-    rowin[j] = yj < ny;
-    ok[j] = rowin[j] && xin;
-    rowo[j] = static_cast<uint32_t>(min(yj, ny - 1)) * static_cast<uint32_t>(nx) * ES;
-    rowo_f[j] = static_cast<uint32_t>(min(yj, ny - 1)) * static_cast<uint32_t>(nx) * 4u;
-    gyv[j] = rowin[j] ? a.gy[yj] : 0.f;
+    const bool ok = yj < ny && xin;
+    const uint32_t e = static_cast<uint32_t>(yj) * static_cast<uint32_t>(nx) + static_cast<uint32_t>(x);
+    vrow[j] = ok ? e * ES : kOOB;
+    vrow_f[j] = ok ? e * 4u : kOOB;
+    gyv[j] = yj < ny ? a.gy[yj] : 0.f;
     ryi[j] = -1;
-    if (a.box.cnx > 0 && rowin[j]) {
+    if (a.box.cnx > 0 && yj < ny) {
       const int d = yj - a.box.y0;
       if (d >= 0 && d % a.box.sy == 0 && d / a.box.sy < a.box.cny) ryi[j] = d / a.box.sy;
     }
-    if (!ADJ && a.sx >= 0 && x == a.sx && yj == a.sy) srcj = j;
+    qrow[j] = (!ADJ && a.sx >= 0 && a.sx >= x && a.sx < x + VEC && yj == a.sy) ? 1.f : 0.f;
   }
-  const uint32_t vo = xl * ES, vo_f = xl * 4u;  // lane byte offsets
   // y-halo rows of this wavefront: halo row r = w + BY*i (r < R above the tile, else below)
-  bool yhin[NYH], yhok[NYH];
   int yhlds[NYH];
-  uint32_t yho[NYH], yho_f[NYH];
+  uint32_t vyh[NYH], vyh_f[NYH];
 #pragma unroll
   for (int i = 0; i < NYH; ++i) {
     const int r = w + BY * i;
-    yhin[i] = r < 2 * R;
+    const bool yhin = r < 2 * R;
     const int lr = r < R ? r : TY + r;
     const int gyy = y0 - R + lr;
-    yhok[i] = yhin[i] && gyy >= 0 && gyy < ny && xin;
-    yhlds[i] = yhin[i] ? lr * LW + R : DUMMY;
-    const uint32_t row = static_cast<uint32_t>(min(max(gyy, 0), ny - 1)) * static_cast<uint32_t>(nx);
-    yho[i] = row * ES;
-    yho_f[i] = row * 4u;
+    const bool ok = yhin && gyy >= 0 && gyy < ny && xin;
+    yhlds[i] = yhin ? lr * LW + R + VEC * lane : DUMMY + VEC * lane;
+    const uint32_t e = static_cast<uint32_t>(gyy) * static_cast<uint32_t>(nx) + static_cast<uint32_t>(x);
+    vyh[i] = ok ? e * ES : kOOB;
+    vyh_f[i] = ok ? e * 4u : kOOB;
   }
   // x-halo: lane l < 8*RY covers row l/8 of this wavefront, column l%8
   int xhlds = DUMMY + lane;
-  bool xhok = false;
-  uint32_t xho = 0, xho_f = 0;
+  uint32_t vxh = kOOB, vxh_f = kOOB;
   if (lane < 8 * RY) {
     const int j = lane >> 3, c = lane & 7;
-    const int gxx = c < R ? x0 - R + c : x0 + kTileX + (c - R);
+    const int gxx = c < R ? x0 - R + c : x0 + TX + (c - R);
     const int yj = yb + j;
-    xhlds = (R + w * RY + j) * LW + (c < R ? c : kTileX + c);
-    xhok = gxx >= 0 && gxx < nx && yj < ny;
-    const uint32_t e = static_cast<uint32_t>(min(yj, ny - 1)) * static_cast<uint32_t>(nx) +
-                       static_cast<uint32_t>(min(max(gxx, 0), nx - 1));
-    xho = e * ES;
-    xho_f = e * 4u;
+    xhlds = (R + w * RY + j) * LW + (c < R ? c : TX + c);
+    if (gxx >= 0 && gxx < nx && yj < ny) {
+      const uint32_t e = static_cast<uint32_t>(yj) * static_cast<uint32_t>(nx) + static_cast<uint32_t>(gxx);
+      vxh = e * ES;
+      vxh_f = e * 4u;
+    }
   }
-
-  const raw *U = static_cast<const raw *>(a.cur);
-  const raw *P = static_cast<const raw *>(a.prev);
-  raw *O = static_cast<raw *>(a.out);
 
   auto rec_plane = [&](int z) {  // receiver-box index of plane z, or -1
     int rzi = -1;
@@ -287,190 +406,242 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
     }
     return rzi;
   };
-  const rsrc_t rgz = make_rsrc(a.gz, static_cast<uint32_t>(nz) * 4u);
+  // per-plane tables, nz + kPadZ entries: the padding planes read sponge
+  // factor 0 and receiver index -1
+  const rsrc_t rgz = make_rsrc(a.gz, static_cast<uint32_t>(a.nz + kPadZ) * 4u);
+  const rsrc_t rrz = make_rsrc(a.rz, static_cast<uint32_t>(a.nz + kPadZ) * 4u);
   // residual row of this launch (adjoint); the resource covers exactly that
-  // row.  Its loads are unconditional, so without receivers it points at the
-  // (always valid) z table instead.
+  // row.  Without receivers it has no records (its loads return zero).
   const bool has_res = ADJ && a.resid != nullptr && a.nrec > 0;
   const rsrc_t rres = has_res ? make_rsrc(a.resid + static_cast<size_t>(a.resid_row) * a.nrec,
                                           static_cast<uint32_t>(a.nrec) * 4u)
-                              : make_rsrc(a.gz, 4u);
+                              : rnull;
 
-  using StageT = Stage<raw, RY, NYH, ADJ>;
   auto load_stage = [&](StageT &st, int z) {
-    const size_t zc = static_cast<size_t>(z) * plane;
-    const size_t zl = static_cast<size_t>(min(z + R, nz - 1)) * plane;
-    st.gz = Buf<float>::ld<0>(rgz, 0u, static_cast<uint32_t>(z) * 4u);
-    const rsrc_t rl = make_rsrc(U + zl, pbytes);
-    const rsrc_t rc = make_rsrc(U + zc, pbytes);
-    const rsrc_t rp = make_rsrc(P + zc, pbytes);
-    const rsrc_t rm = make_rsrc(a.m + zc, pbytes_f);
+    const uint32_t sl = so(z + R), slf = so_f(z + R);
+    const uint32_t sc = so(z), scf = so_f(z);
+    st.gz = __uint_as_float(ld_words<4, 0>(rgz, 0u, static_cast<uint32_t>(z) * 4u).w[0]);
+    st.rz = static_cast<int>(ld_words<4, 0>(rrz, 0u, static_cast<uint32_t>(z) * 4u).w[0]);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      st.lead[j] = B::template ld<0>(rl, vo, rowo[j]);
-      st.p[j] = B::template ld<kNT>(rp, vo, rowo[j]);
-      st.m[j] = Buf<float>::ld<kNT>(rm, vo_f, rowo_f[j]);
+      st.lead[j] = ld_words<NA, 0>(rU, vrow[j], sl);
+      st.p[j] = ld_words<NA, kNT>(rP, vrow[j], sc);
+      st.m[j] = ld_words<NF, kNT>(rM, vrow_f[j], scf);
     }
 #pragma unroll
-    for (int i = 0; i < NYH; ++i) st.yh[i] = B::template ld<0>(rc, vo, yho[i]);
-    st.xh = B::template ld<0>(rc, xho, 0);
-    if (ADJ) {
-      const rsrc_t fl = make_rsrc(a.fwd + zl, pbytes_f);
-      const rsrc_t fc = make_rsrc(a.fwd + zc, pbytes_f);
-      const rsrc_t ri = make_rsrc(a.img + zc, pbytes_f);
+    for (int i = 0; i < NYH; ++i) st.yh[i] = ld_words<NA, 0>(rU, vyh[i], sc);
+    st.xh = ld_words<S == kF32 ? 4 : 2, 0>(rU, vxh, sc);
+    if constexpr (ADJ) {
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
-        st.leadF[j] = Buf<float>::ld<0>(fl, vo_f, rowo_f[j]);
-        st.img[j] = Buf<float>::ld<kNT>(ri, vo_f, rowo_f[j]);
+        st.leadF[j] = ld_words<NF, 0>(rF, vrow_f[j], slf);
+        st.img[j] = ld_words<NF, kNT>(rI, vrow_f[j], scf);
       }
 #pragma unroll
-      for (int i = 0; i < NYH; ++i) st.yhF[i] = Buf<float>::ld<0>(fc, vo_f, yho_f[i]);
-      st.xhF = Buf<float>::ld<0>(fc, xho_f, 0);
+      for (int i = 0; i < NYH; ++i) st.yhF[i] = ld_words<NF, 0>(rF, vyh_f[i], scf);
+      st.xhF = __uint_as_float(ld_words<4, 0>(rF, vxh_f, scf).w[0]);
       const int rzi = rec_plane(z);
 #pragma unroll
-      for (int j = 0; j < RY; ++j) {
-        const bool at = rzi >= 0 && ryi[j] >= 0 && rxi >= 0;
-        const uint32_t ridx = at ? static_cast<uint32_t>((rzi * a.box.cny + ryi[j]) * a.box.cnx + rxi) : 0u;
-        st.res[j] = Buf<float>::ld<0>(rres, ridx * 4u, 0u);
-      }
+      for (int j = 0; j < RY; ++j)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+          const bool at = rzi >= 0 && ryi[j] >= 0 && rxi[i] >= 0;
+          const uint32_t ridx =
+              at ? static_cast<uint32_t>((rzi * a.box.cny + ryi[j]) * a.box.cnx + rxi[i]) * 4u : kOOB;
+          st.res[j][i] = __uint_as_float(ld_words<4, 0>(rres, ridx, 0u).w[0]);
+        }
     }
   };
 
   // ---- prologue: queue slot (p - zb + R) mod 9 holds plane p; stages hold planes zb .. zb+PD-1
-  float q[kQ][RY];
-  float qF[ADJ ? kQ : 1][RY];
+  float q[kQ][RY][VEC];
+  float qF[ADJ ? kQ : 1][RY][VEC];
 #pragma unroll
-  for (int i = 0; i < 2 * R; ++i) {
-    const int zz = zb - R + i;
-    const bool zok = zz >= 0 && zz < nz;
-    const rsrc_t r = make_rsrc(U + static_cast<size_t>(min(max(zz, 0), nz - 1)) * plane, pbytes);
-    const rsrc_t rf = make_rsrc(a.fwd + static_cast<size_t>(min(max(zz, 0), nz - 1)) * plane, pbytes_f);
+  for (int k = 0; k < 2 * R; ++k) {
+    const int zz = zb - R + k;
+    const bool zok = zz >= 0;
+    const rsrc_t r = zok ? rU : rnull;
+    const rsrc_t rf = zok ? rF : rnull;
+    const uint32_t s0 = zok ? so(zz) : 0u, s0f = zok ? so_f(zz) : 0u;
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      const float u = C::dec(B::template ld<0>(r, vo, rowo[j])) * inv_cur;
-      q[i][j] = (zok && ok[j]) ? u : 0.f;
-      if (ADJ) {
-        const float f = Buf<float>::ld<0>(rf, vo_f, rowo_f[j]);
-        qF[i][j] = (zok && ok[j]) ? f : 0.f;
+      const Words<NA> t = ld_words<NA, 0>(r, vrow[j], s0);
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) q[k][j][i] = row_get<S>(t, i) * inv_cur;
+      if constexpr (ADJ) {
+        const Words<NF> tf = ld_words<NF, 0>(rf, vrow_f[j], s0f);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) qF[k][j][i] = __uint_as_float(tf.w[i]);
       }
     }
   }
   StageT stg[PD];
 #pragma unroll
-  for (int s = 0; s < PD; ++s)
-    if (zb + s < ze) load_stage(stg[s], zb + s);
+  for (int s = 0; s < PD; ++s) load_stage(stg[s], zb + s);
 
   const float wsrc = (!ADJ && a.sx >= 0) ? a.wavelet[n] * a.src_scale : 0.f;
   float amax_loc = 0.f, amaxv_loc = 0.f;
+
+  // Laplacian of Eq. 1 at the VEC nodes of row j of this lane: centre and z
+  // neighbours from the queue Q, x neighbours from a window of the LDS row,
+  // y neighbours from this lane's own rows when they lie in the strip, else
+  // from the LDS rows above and below.
+  auto laplacian = [&](const float (&Q)[kQ][RY][VEC], const float *Lp, int cs, int s0, int j, float *lap)
+      __attribute__((always_inline)) {
+    const float *row = Lp + (R + w * RY + j) * LW + VEC * lane;  // window start: column x - R
+    float win[VEC + 2 * R];
+#pragma unroll
+    for (int k = 0; k < (VEC + 2 * R) / VEC; ++k)
+      if (VEC > 1 || k != R) lds_get<VEC>(row + VEC * k, win + VEC * k);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      if (VEC == 1) win[R] = Q[cs][j][0];
+      lap[i] = a.c.k0 * Q[cs][j][i];
+    }
+#pragma unroll
+    for (int m = 1; m <= R; ++m) {
+      float yp[VEC], ym[VEC];
+      if (j + m < RY) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) yp[i] = Q[cs][(j + m) % RY][i];
+      } else {
+        lds_get<VEC>(row + m * LW + R, yp);
+      }
+      if (j - m >= 0) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) ym[i] = Q[cs][(j - m + RY) % RY][i];
+      } else {
+        lds_get<VEC>(row - m * LW + R, ym);
+      }
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) {
+        lap[i] = fmaf(a.c.kx[m - 1], win[R + i + m] + win[R + i - m], lap[i]);
+        lap[i] = fmaf(a.c.ky[m - 1], yp[i] + ym[i], lap[i]);
+        lap[i] = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i] + Q[(s0 + R - m + kQ) % kQ][j][i], lap[i]);
+      }
+    }
+  };
 
   for (int zs = zb; zs < ze; zs += kQ) {
     // nine planes per trip with compile-time queue slots and stage indices, so
     // the queue rotates by register renaming (a runtime index would move the
     // queue into scratch memory)
-    // Positions past the chunk end (only in a trip that straddles it) run on
-    // clamped in-bounds planes with their stores switched off: no position is
-    // skipped, so no control-flow join makes the compiler drain the loads.
     static_for<kQ>([&](auto sc) __attribute__((always_inline)) {
       constexpr int s = decltype(sc)::value;
-      const int z = min(zs + s, ze - 1);
-      const bool live = zs + s < ze;
-      const int cslot = (s + R) % kQ;          // plane z
+      const int z = zs + s;
+      constexpr int cslot = (s + R) % kQ;  // plane z
       StageT &cs = stg[s % PD];
-      // buffer parity follows the unclamped position: consecutive positions
-      // must alternate even when the plane index is clamped
-      const int par = (zs + s - zb) & 1;
+      const int par = (z - zb) & 1;
       float *L = lds[par];
       float *LF = ldsF[ADJ ? par : 0];
-      const bool lok = z + R < nz;
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
-        q[(s + 2 * R) % kQ][j] = (ok[j] && lok) ? C::dec(cs.lead[j]) * inv_cur : 0.f;
-        L[(R + w * RY + j) * LW + R + lane] = q[cslot][j];
-        if (ADJ) {
-          qF[(s + 2 * R) % kQ][j] = (ok[j] && lok) ? cs.leadF[j] : 0.f;
-          LF[(R + w * RY + j) * LW + R + lane] = qF[cslot][j];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) q[(s + 2 * R) % kQ][j][i] = row_get<S>(cs.lead[j], i) * inv_cur;
+        lds_put<VEC>(L + (R + w * RY + j) * LW + R + VEC * lane, q[cslot][j]);
+        if constexpr (ADJ) {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) qF[(s + 2 * R) % kQ][j][i] = __uint_as_float(cs.leadF[j].w[i]);
+          lds_put<VEC>(LF + (R + w * RY + j) * LW + R + VEC * lane, qF[cslot][j]);
         }
       }
 #pragma unroll
-      for (int i = 0; i < NYH; ++i) {
-        L[yhlds[i] + lane] = yhok[i] ? C::dec(cs.yh[i]) * inv_cur : 0.f;
-        if (ADJ) LF[yhlds[i] + lane] = yhok[i] ? cs.yhF[i] : 0.f;
-      }
-      L[xhlds] = xhok ? C::dec(cs.xh) * inv_cur : 0.f;
-      if (ADJ) LF[xhlds] = xhok ? cs.xhF : 0.f;
-      float pc[RY], mc[RY], ic[RY], rc[RY];
+      for (int k = 0; k < NYH; ++k) {
+        float t[VEC];
 #pragma unroll
-      for (int j = 0; j < RY; ++j) {
-        pc[j] = C::dec(cs.p[j]) * inv_prev;
-        mc[j] = cs.m[j];
-        ic[j] = ADJ ? cs.img[j] : 0.f;
-        rc[j] = ADJ ? cs.res[j] : 0.f;
+        for (int i = 0; i < VEC; ++i) t[i] = row_get<S>(cs.yh[k], i) * inv_cur;
+        lds_put<VEC>(L + yhlds[k], t);
+        if constexpr (ADJ) {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) t[i] = __uint_as_float(cs.yhF[k].w[i]);
+          lds_put<VEC>(LF + yhlds[k], t);
+        }
       }
+      L[xhlds] = row_get<S>(cs.xh, 0) * inv_cur;
+      if constexpr (ADJ) LF[xhlds] = cs.xhF;
+      float pc[RY][VEC], mc[RY][VEC], ic[RY][VEC], rc[RY][VEC];
+#pragma unroll
+      for (int j = 0; j < RY; ++j)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+          pc[j][i] = row_get<S>(cs.p[j], i) * inv_prev;
+          mc[j][i] = __uint_as_float(cs.m[j].w[i]);
+          ic[j][i] = ADJ ? __uint_as_float(cs.img[ADJ ? j : 0].w[i]) : 0.f;
+          rc[j][i] = ADJ ? cs.res[ADJ ? j : 0][ADJ ? i : 0] : 0.f;
+        }
       const float gzv = cs.gz;
-      load_stage(cs, min(z + PD, ze - 1));  // past the chunk end: a repeat of the last plane, unused
+      const int rzi = ADJ ? rec_plane(z) : __builtin_amdgcn_readfirstlane(cs.rz);
+      load_stage(cs, z + PD);  // past the chunk end: planes of the next chunk or padding, unused
       __syncthreads();
 
-      const size_t zc = static_cast<size_t>(z) * plane;
-      const rsrc_t ro = make_rsrc(O + zc, pbytes);
-      const rsrc_t rvo = make_rsrc((S != kF32 ? static_cast<raw *>(a.vout) : O) + zc, pbytes);
-      const int rzi = rec_plane(z);
+      const uint32_t sz0 = so(z), sz0f = so_f(z);
+      // source term of this plane, per column of the lane's VEC nodes
+      float wsp[VEC];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) wsp[i] = (!ADJ && z == a.sz && i == srci) ? wsrc : 0.f;
+      float outv[RY][VEC];
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
-        const float *row = L + (R + w * RY + j) * LW + R + lane;
-        const float c = q[cslot][j];
-        float lap = a.c.k0 * c;
+        float lap[VEC];
+        laplacian(q, L, cslot, s, j, lap);
+        const float gyz = gyv[j] * gzv;
+        float v[VEC], vv[VEC];
 #pragma unroll
-        for (int m = 1; m <= R; ++m) {
-          // y neighbours come from this thread's own rows when they lie in the strip
-          const float yp = (j + m < RY) ? q[cslot][(j + m) % RY] : row[m * LW];
-          const float ym = (j - m >= 0) ? q[cslot][(j - m + RY) % RY] : row[-m * LW];
-          lap = fmaf(a.c.kx[m - 1], row[m] + row[-m], lap);
-          lap = fmaf(a.c.ky[m - 1], yp + ym, lap);
-          lap = fmaf(a.c.kz[m - 1], q[(s + R + m) % kQ][j] + q[(s + R - m + kQ) % kQ][j], lap);
+        for (int i = 0; i < VEC; ++i) {
+          const float c = q[cslot][j][i];
+          if (ADJ) lap[i] += rc[j][i];  // zero off the receivers
+          const float g = gxv[i] * gyz;
+          if (S == kF32) {  // A^{n+1} = g (2 A^n - g A^{n-1} + m L A^n + q)
+            float t = fmaf(-g, pc[j][i], 2.f * c);
+            t = fmaf(mc[j][i], lap[i], t);
+            if (!ADJ) t = fmaf(qrow[j], wsp[i], t);
+            v[i] = t * g;
+          } else {  // V^{n+1} = g (V^n + m L A^n + q),  A^{n+1} = g A^n + V^{n+1}
+            float t = fmaf(mc[j][i], lap[i], pc[j][i]);
+            t = fmaf(qrow[j], wsp[i], t);
+            vv[i] = t * g;
+            v[i] = fmaf(g, c, vv[i]);
+          }
         }
-        const bool at_rec = rzi >= 0 && ryi[j] >= 0 && rxi >= 0;
-        const int ridx = at_rec ? (rzi * a.box.cny + ryi[j]) * a.box.cnx + rxi : 0;
-        if (ADJ && at_rec) lap += rc[j];
-        const float g = gxv * (gyv[j] * gzv);
-        float v, vv = 0.f;
-        if (S == kF32) {  // A^{n+1} = g (2 A^n - g A^{n-1} + m L A^n + q)
-          v = fmaf(-g, pc[j], 2.f * c);
-          v = fmaf(mc[j], lap, v);
-          if (!ADJ && srcj == j && z == a.sz) v += wsrc;
-          v *= g;
-        } else {  // V^{n+1} = g (V^n + m L A^n + q),  A^{n+1} = g A^n + V^{n+1}
-          vv = fmaf(mc[j], lap, pc[j]);
-          if (srcj == j && z == a.sz) vv += wsrc;
-          vv *= g;
-          v = fmaf(g, c, vv);
-        }
-        if (ok[j] && live) {
-          const raw r = C::enc(v * s_next);
-          B::template st<kNT>(r, ro, vo, rowo[j]);
-          const float stored = C::dec(r);
-          if (S != kF32) {
-            const raw rv = C::enc(vv * sv_next);
-            B::template st<kNT>(rv, rvo, vo, rowo[j]);
+        if (S == kF32) {
+          st_words<NA, kNT>(row_put<S, VEC>(v), rO, vrow[j], sz0);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) outv[j][i] = v[i];
+        } else {
+          float sa[VEC], sv[VEC];
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) {
+            sa[i] = v[i] * s_next;
+            sv[i] = vv[i] * sv_next;
+          }
+          const Words<NA> ra = row_put<S, VEC>(sa), rv = row_put<S, VEC>(sv);
+          st_words<NA, kNT>(ra, rO, vrow[j], sz0);
+          st_words<NA, kNT>(rv, rVo, vrow[j], sz0);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) {
+            const float stored = row_get<S>(ra, i);
+            outv[j][i] = stored * inv_next;
             amax_loc = fmaxf(amax_loc, fabsf(stored));
-            amaxv_loc = fmaxf(amaxv_loc, fabsf(C::dec(rv)));
-          }
-          if (!ADJ && at_rec) a.traces[static_cast<size_t>(n) * a.nrec + ridx] = stored * inv_next;
-          if (ADJ) {
-            const float *rowF = LF + (R + w * RY + j) * LW + R + lane;
-            const float cF = qF[cslot][j];
-            float lapF = a.c.k0 * cF;
-#pragma unroll
-            for (int m = 1; m <= R; ++m) {
-              const float yp = (j + m < RY) ? qF[cslot][(j + m) % RY] : rowF[m * LW];
-              const float ym = (j - m >= 0) ? qF[cslot][(j - m + RY) % RY] : rowF[-m * LW];
-              lapF = fmaf(a.c.kx[m - 1], rowF[m] + rowF[-m], lapF);
-              lapF = fmaf(a.c.ky[m - 1], yp + ym, lapF);
-              lapF = fmaf(a.c.kz[m - 1], qF[(s + R + m) % kQ][j] + qF[(s + R - m + kQ) % kQ][j], lapF);
-            }
-            const rsrc_t ri = make_rsrc(a.img + zc, pbytes_f);
-            Buf<float>::st<kNT>(fmaf(c, lapF, ic[j]), ri, vo_f, rowo_f[j]);
+            amaxv_loc = fmaxf(amaxv_loc, fabsf(row_get<S>(rv, i)));
           }
         }
+        if constexpr (ADJ) {
+          float lapF[VEC], im[VEC];
+          laplacian(qF, LF, cslot, s, j, lapF);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) im[i] = fmaf(q[cslot][j][i], lapF[i], ic[j][i]);
+          st_words<NF, kNT>(row_put<kF32, VEC>(im), rI, vrow_f[j], sz0f);
+        }
+      }
+      // receiver samples of A^{n+1} (forward), in the plane's own uniform branch
+      if (!ADJ && rzi >= 0) {
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+#pragma unroll
+          for (int i = 0; i < VEC; ++i)
+            if (ryi[j] >= 0 && rxi[i] >= 0)
+              a.traces[static_cast<size_t>(n) * a.nrec + (rzi * a.box.cny + ryi[j]) * a.box.cnx + rxi[i]] =
+                  outv[j][i];
       }
     });
   }
@@ -587,7 +758,7 @@ __global__ void decode_prev_kernel(const typename Codec<S>::raw *__restrict__ fa
     const int x = static_cast<int>(i % nx);
     const int y = static_cast<int>((i / nx) % ny);
     const int z = static_cast<int>(i / (static_cast<size_t>(nx) * ny));
-    const float g = gx[x] * (gy[y] * gz[z]);
+    const float g = gx[x] * (gy[y] * gz[z]);  // the step kernel's association
     out[i] = (Codec<S>::dec(fa[i]) * ia - Codec<S>::dec(fv[i]) * iv) / g;
   }
 }
@@ -642,16 +813,34 @@ unsigned grid_for(size_t n, unsigned block) {
   return static_cast<unsigned>(want < 1 ? 1 : (want > cap ? cap : want));
 }
 
-// (BY, RY, PD) per variant
-constexpr Variant kVariants[] = {{8, 4, 3}, {4, 8, 1}, {4, 4, 3}, {8, 2, 3},
-                                 {4, 4, 1}, {8, 4, 1}, {2, 8, 1}, {4, 2, 3}};
+// Tile shapes (BY, RY, PD, VEC) of the step kernel; variant 0 is also the
+// shape the runtime's automatic choice falls back to.
+#define WAVE_VARIANTS(X) \
+  X(0, 8, 4, 3, 1)       \
+  X(1, 4, 8, 1, 1)       \
+  X(2, 4, 4, 3, 1)       \
+  X(3, 8, 2, 3, 1)       \
+  X(4, 4, 4, 1, 1)       \
+  X(5, 8, 4, 1, 1)       \
+  X(6, 2, 8, 1, 1)       \
+  X(7, 4, 2, 3, 1)       \
+  X(8, 8, 2, 3, 2)       \
+  X(9, 8, 2, 1, 4)       \
+  X(10, 4, 4, 1, 2)      \
+  X(11, 8, 4, 1, 2)      \
+  X(12, 8, 1, 3, 4)      \
+  X(13, 4, 2, 3, 2)
+
+#define WAVE_VARIANT_INFO(id, by, ry, pd, vec) {by, ry, pd, vec},
+constexpr Variant kVariants[] = {WAVE_VARIANTS(WAVE_VARIANT_INFO)};
+#undef WAVE_VARIANT_INFO
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <int S, int BY, int RY, int PD, bool ADJ>
+template <int S, int BY, int RY, int PD, int VEC, bool ADJ>
 int blocks_per_cu() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(step_kernel<S, BY, RY, PD, ADJ>),
-                                                   64 * BY, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void *>(step_kernel<S, BY, RY, PD, VEC, ADJ>), 64 * BY, 0) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
@@ -659,36 +848,28 @@ int blocks_per_cu() {
 template <int S, bool ADJ>
 int blocks_variant(int v) {
   switch (v) {
-    case 0: return blocks_per_cu<S, 8, 4, 3, ADJ>();
-    case 1: return blocks_per_cu<S, 4, 8, 1, ADJ>();
-    case 2: return blocks_per_cu<S, 4, 4, 3, ADJ>();
-    case 3: return blocks_per_cu<S, 8, 2, 3, ADJ>();
-    case 4: return blocks_per_cu<S, 4, 4, 1, ADJ>();
-    case 5: return blocks_per_cu<S, 8, 4, 1, ADJ>();
-    case 6: return blocks_per_cu<S, 2, 8, 1, ADJ>();
-    case 7: return blocks_per_cu<S, 4, 2, 3, ADJ>();
+#define WAVE_VARIANT_CASE(id, by, ry, pd, vec) \
+  case id: return blocks_per_cu<S, by, ry, pd, vec, ADJ>();
+    WAVE_VARIANTS(WAVE_VARIANT_CASE)
+#undef WAVE_VARIANT_CASE
     default: return 1;
   }
 }
 
-template <int S, int BY, int RY, int PD, bool ADJ>
+template <int S, int BY, int RY, int PD, int VEC, bool ADJ>
 hipError_t launch_one(const StepArgs &a, hipStream_t s) {
   const unsigned grid = static_cast<unsigned>((a.total_tiles + 7) / 8 * 8);
-  hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, ADJ>), dim3(grid), dim3(64 * BY), 0, s, a);
+  hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, ADJ>), dim3(grid), dim3(64 * BY), 0, s, a);
   return hipGetLastError();
 }
 
 template <int S, bool ADJ>
 hipError_t launch_variant(int v, const StepArgs &a, hipStream_t s) {
   switch (v) {
-    case 0: return launch_one<S, 8, 4, 3, ADJ>(a, s);
-    case 1: return launch_one<S, 4, 8, 1, ADJ>(a, s);
-    case 2: return launch_one<S, 4, 4, 3, ADJ>(a, s);
-    case 3: return launch_one<S, 8, 2, 3, ADJ>(a, s);
-    case 4: return launch_one<S, 4, 4, 1, ADJ>(a, s);
-    case 5: return launch_one<S, 8, 4, 1, ADJ>(a, s);
-    case 6: return launch_one<S, 2, 8, 1, ADJ>(a, s);
-    case 7: return launch_one<S, 4, 2, 3, ADJ>(a, s);
+#define WAVE_VARIANT_CASE(id, by, ry, pd, vec) \
+  case id: return launch_one<S, by, ry, pd, vec, ADJ>(a, s);
+    WAVE_VARIANTS(WAVE_VARIANT_CASE)
+#undef WAVE_VARIANT_CASE
     default: return hipErrorInvalidValue;
   }
 }

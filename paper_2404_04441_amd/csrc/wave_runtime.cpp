@@ -23,7 +23,7 @@ constexpr double kC[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct Layout {
-  size_t st, gx, gy, gz, rec_lin, grec, m, fa, fb, fv, ckpt, seg, mua, mub, img, total;
+  size_t st, gx, gy, gz, rz, rec_lin, grec, m, fa, fb, fv, ckpt, seg, mua, mub, img, total;
   int K, nck;
 };
 
@@ -32,8 +32,9 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int validate(const wave_params *p) {
   if (!p) return WAVE_EINVAL;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return WAVE_EINVAL;
-  // one xy plane of float32 must stay below 2^31 bytes (32-bit buffer offsets)
-  if (static_cast<int64_t>(p->nx) * p->ny >= (int64_t(1) << 29)) return WAVE_EINVAL;
+  // at most 2^24 nodes per xy plane: a workgroup's buffer resources span its
+  // z-chunk plus halo planes, and every span must stay below 2^31 bytes
+  if (static_cast<int64_t>(p->nx) * p->ny > (int64_t(1) << 24)) return WAVE_EINVAL;
   if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dz) || !finite_pos(p->dt)) return WAVE_EINVAL;
   if (p->sponge_width < 0 || !std::isfinite(p->sponge_alpha) || p->sponge_alpha < 0.0) return WAVE_EINVAL;
   if (p->storage < WAVE_F32 || p->storage > WAVE_BF16) return WAVE_EINVAL;
@@ -50,6 +51,8 @@ int validate(const wave_params *p) {
     if (p->storage != WAVE_F32 || p->nt_max < 1 || p->ckpt_interval < 0) return WAVE_EINVAL;
   }
   if (p->variant < 0 || p->variant >= variant_count()) return WAVE_EINVAL;
+  // an explicit tile shape with VEC > 1 x nodes per lane needs whole vectors per row
+  if (p->variant > 0 && p->nx % variant_info(p->variant).vec) return WAVE_EINVAL;
   if (p->zchunk < 0 || p->graph_steps < 0) return WAVE_EINVAL;
   return WAVE_OK;
 }
@@ -58,6 +61,8 @@ int plan(const wave_params *p, Layout *L) {
   const int rc = validate(p);
   if (rc) return rc;
   const size_t N = static_cast<size_t>(p->nx) * p->ny * p->nz;
+  // fields the step kernel touches carry kPadZ zero planes after the interior
+  const size_t Np = static_cast<size_t>(p->nx) * p->ny * (static_cast<size_t>(p->nz) + kPadZ);
   const size_t es = p->storage == WAVE_F32 ? 4 : 2;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -68,14 +73,15 @@ int plan(const wave_params *p, Layout *L) {
   L->st = take(sizeof(StepState));
   L->gx = take(4 * static_cast<size_t>(p->nx));
   L->gy = take(4 * static_cast<size_t>(p->ny));
-  L->gz = take(4 * static_cast<size_t>(p->nz));
+  L->gz = take(4 * (static_cast<size_t>(p->nz) + kPadZ));
+  L->rz = take(4 * (static_cast<size_t>(p->nz) + kPadZ));
   L->rec_lin = take(8 * static_cast<size_t>(p->nrec));
   L->grec = take(4 * static_cast<size_t>(p->nrec));
-  L->m = take(4 * N);
-  L->fa = take(es * N);
-  L->fb = take(es * N);
+  L->m = take(4 * Np);
+  L->fa = take(es * Np);
+  L->fb = take(es * Np);
   // 16-bit storage keeps V^n = A^n - g A^{n-1} besides the A ping-pong pair
-  L->fv = p->storage == WAVE_F32 ? off : take(es * N);
+  L->fv = p->storage == WAVE_F32 ? off : take(es * Np);
   L->K = 0;
   L->nck = 0;
   L->ckpt = L->seg = L->mua = L->mub = L->img = off;
@@ -86,11 +92,11 @@ int plan(const wave_params *p, Layout *L) {
     const int nseg = (p->nt_max + K - 1) / K;
     L->K = K;
     L->nck = nseg - 1;
-    L->ckpt = take(4 * N * 2 * static_cast<size_t>(L->nck));
-    L->seg = take(4 * N * static_cast<size_t>(K + 2));
-    L->mua = take(4 * N);
-    L->mub = take(4 * N);
-    L->img = take(4 * N);
+    L->ckpt = take(4 * N * 2 * static_cast<size_t>(L->nck));  // interiors only
+    L->seg = take(4 * Np * static_cast<size_t>(K + 2));
+    L->mua = take(4 * Np);
+    L->mub = take(4 * Np);
+    L->img = take(4 * Np);
   }
   L->total = off;
   return WAVE_OK;
@@ -134,6 +140,61 @@ bool detect_box(const std::vector<int32_t> &rec, int nrec, RecBox *b) {
   return true;
 }
 
+// One tile decomposition of the grid for a step-kernel variant.
+struct Tiling {
+  int variant = 0, tiles_x = 0, tiles_y = 0, nchunks = 0, zchunk = 0, total_tiles = 0;
+};
+
+// Measured-best tile shapes on MI355X (variant indices of the kernel
+// table): 4 x nodes per lane when rows allow it (8 wavefronts x 1 row; for
+// float32 planes above 512 x 512, 8 x 4 rows of 2 nodes), else 2, else 1.
+int auto_variant(const wave_params *p) {
+  const int64_t plane = static_cast<int64_t>(p->nx) * p->ny;
+  if (p->nx % 4 == 0) return (p->storage == WAVE_F32 && plane > (int64_t(1) << 18)) ? 11 : 12;
+  if (p->nx % 2 == 0) return 8;
+  return p->storage == WAVE_F32 ? 0 : 3;
+}
+// The adjoint kernel keeps two z queues: its default is a one-node-per-lane
+// shape that fits in registers (8 wavefronts x 2 rows).
+constexpr int kAdjointVariant = 3;
+
+Tiling make_tiling(const wave_params *p, int variant) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  Tiling t;
+  t.variant = variant;
+  const Variant v = variant_info(variant);
+  const int TY = v.by * v.ry;
+  const int TX = kTileX * v.vec;
+  t.tiles_x = (nx + TX - 1) / TX;
+  t.tiles_y = (ny + TY - 1) / TY;
+  int zc = p->zchunk;
+  if (zc > 0) zc = (zc + 8) / 9 * 9;  // the kernel advances nine planes per trip
+  if (zc <= 0) {
+    // as many long-lived workgroups as fit on the 256 CUs at once: long
+    // z-chunks re-read fewer overlap planes and keep the prefetch pipeline full
+    const int per_plane = t.tiles_x * t.tiles_y;
+    const int want = 256 * step_blocks_per_cu(p->storage, variant);
+    const int chunks = std::max(1, (want + per_plane / 2) / per_plane);
+    zc = std::max(18, (nz + chunks - 1) / chunks);
+    zc = (zc + 8) / 9 * 9;
+  }
+  // a workgroup's buffer resources span its z-chunk, R halo planes below and
+  // kMaxPD + R prefetch and halo planes above; every span (float32 fields)
+  // must stay below 2^31 bytes.  With at most 2^24 nodes per plane this
+  // leaves at least one nine-plane trip.
+  const int64_t plane_f = 4 * static_cast<int64_t>(nx) * ny;
+  const int zc_max = (static_cast<int>(((int64_t(1) << 31) - 1) / plane_f) - (2 * kRadius + kMaxPD)) / 9 * 9;
+  if (zc > zc_max) {  // equal chunks that fit
+    const int k = (nz + zc_max - 1) / zc_max;
+    zc = ((nz + k - 1) / k + 8) / 9 * 9;
+    if (zc > zc_max) zc = zc_max;
+  }
+  t.zchunk = zc;
+  t.nchunks = (nz + zc - 1) / zc;
+  t.total_tiles = t.tiles_x * t.tiles_y * t.nchunks;
+  return t;
+}
+
 }  // namespace
 
 struct wave_ctx {
@@ -144,15 +205,17 @@ struct wave_ctx {
   Layout L{};
   StepState *st = nullptr;
   float *gx = nullptr, *gy = nullptr, *gz = nullptr, *m = nullptr, *grec = nullptr;
+  int32_t *rz = nullptr;
   int64_t *rec_lin = nullptr;
   void *fa = nullptr, *fb = nullptr, *fv = nullptr;
-  size_t N = 0;
-  int n = 0;  // host mirror of the step counter
+  size_t N = 0;   // interior nodes
+  size_t Np = 0;  // nodes of a padded field (interior + kPadZ zero planes)
+  int n = 0;      // host mirror of the step counter
   Coef c{};
   float src_scale = 0.f, gamma = 0.f;
   RecBox box{};
   bool fused_rec = false;
-  int tiles_x = 0, tiles_y = 0, nchunks = 0, zchunk = 0, total_tiles = 0;
+  Tiling fwd{}, adj{};  // forward and adjoint step kernels
   // graph replay cache: one graph per buffer parity
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   const float *g_wavelet = nullptr;
@@ -173,20 +236,21 @@ namespace {
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? WAVE_OK : WAVE_EHIP; }
 
-StepArgs base_args(const wave_ctx *w) {
+StepArgs base_args(const wave_ctx *w, const Tiling &t) {
   StepArgs a{};
   a.m = w->m;
   a.gx = w->gx;
   a.gy = w->gy;
   a.gz = w->gz;
+  a.rz = w->rz;
   a.nx = w->p.nx;
   a.ny = w->p.ny;
   a.nz = w->p.nz;
-  a.tiles_x = w->tiles_x;
-  a.tiles_y = w->tiles_y;
-  a.nchunks = w->nchunks;
-  a.zchunk = w->zchunk;
-  a.total_tiles = w->total_tiles;
+  a.tiles_x = t.tiles_x;
+  a.tiles_y = t.tiles_y;
+  a.nchunks = t.nchunks;
+  a.zchunk = t.zchunk;
+  a.total_tiles = t.total_tiles;
   a.c = w->c;
   a.sx = w->p.src[0] >= 0 ? w->p.src[0] : -1;
   a.sy = w->p.src[1];
@@ -201,7 +265,7 @@ StepArgs base_args(const wave_ctx *w) {
 // Enqueue `count` forward steps starting at device counter st->n (and host
 // n), then advance the counter.  sample = write traces.
 int enqueue_steps(wave_ctx *w, int count, const float *wavelet, float *traces, bool sample) {
-  StepArgs a = base_args(w);
+  StepArgs a = base_args(w, w->fwd);
   a.wavelet = wavelet;
   a.traces = traces;
   if (sample && w->fused_rec) a.box = w->box;
@@ -212,7 +276,7 @@ int enqueue_steps(wave_ctx *w, int count, const float *wavelet, float *traces, b
     a.prev = w->p.storage == WAVE_F32 ? w->field(parity ^ 1) : w->fv;
     a.vout = w->fv;
     a.k = k;
-    int rc = hip_rc(launch_step(w->p.storage, w->p.variant, false, a, w->stream));
+    int rc = hip_rc(launch_step(w->p.storage, w->fwd.variant, false, a, w->stream));
     if (rc) return rc;
     if (sample && !w->fused_rec && w->p.nrec > 0) {
       rc = hip_rc(launch_gather(w->p.storage, a.out, w->rec_lin, w->p.nrec, traces, w->st, k, w->stream));
@@ -279,9 +343,9 @@ int do_step(wave_ctx *w, int nsteps, const float *wavelet, float *traces) {
 
 int do_reset(wave_ctx *w) {
   const size_t es = w->p.storage == WAVE_F32 ? 4 : 2;
-  int rc = hip_rc(launch_fill_zero(w->fa, es * w->N, w->stream));
-  if (!rc) rc = hip_rc(launch_fill_zero(w->fb, es * w->N, w->stream));
-  if (!rc && w->fv) rc = hip_rc(launch_fill_zero(w->fv, es * w->N, w->stream));
+  int rc = hip_rc(launch_fill_zero(w->fa, es * w->Np, w->stream));
+  if (!rc) rc = hip_rc(launch_fill_zero(w->fb, es * w->Np, w->stream));
+  if (!rc && w->fv) rc = hip_rc(launch_fill_zero(w->fv, es * w->Np, w->stream));
   if (!rc) rc = hip_rc(launch_reset_state(w->st, w->stream));
   if (!rc) w->n = 0;
   return rc;
@@ -332,6 +396,7 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   w->gx = reinterpret_cast<float *>(w->ws + L.gx);
   w->gy = reinterpret_cast<float *>(w->ws + L.gy);
   w->gz = reinterpret_cast<float *>(w->ws + L.gz);
+  w->rz = reinterpret_cast<int32_t *>(w->ws + L.rz);
   w->rec_lin = reinterpret_cast<int64_t *>(w->ws + L.rec_lin);
   w->grec = reinterpret_cast<float *>(w->ws + L.grec);
   w->m = reinterpret_cast<float *>(w->ws + L.m);
@@ -340,6 +405,7 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   w->fv = p->storage == WAVE_F32 ? nullptr : w->ws + L.fv;
   const int nx = p->nx, ny = p->ny, nz = p->nz;
   w->N = static_cast<size_t>(nx) * ny * nz;
+  w->Np = static_cast<size_t>(nx) * ny * (static_cast<size_t>(nz) + kPadZ);
 
   // FP64 host tables
   const double ix2 = 1.0 / (p->dx * p->dx), iy2 = 1.0 / (p->dy * p->dy), iz2 = 1.0 / (p->dz * p->dz);
@@ -352,7 +418,7 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   w->src_scale = static_cast<float>(p->dt * p->dt / (p->dx * p->dy * p->dz));
   const std::vector<float> gx = sponge_table(nx, p->sponge_width, p->sponge_alpha);
   const std::vector<float> gy = sponge_table(ny, p->sponge_width, p->sponge_alpha);
-  const std::vector<float> gz = sponge_table(nz, p->sponge_width, p->sponge_alpha);
+  std::vector<float> gz = sponge_table(nz, p->sponge_width, p->sponge_alpha);
   std::vector<int64_t> lin(p->nrec);
   std::vector<float> grec(p->nrec);
   for (int r = 0; r < p->nrec; ++r) {
@@ -362,28 +428,16 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   }
   w->fused_rec = detect_box(w->rec, p->nrec, &w->box);
   if (!w->fused_rec) w->box = RecBox{};
+  // receiver-box plane index of every z-plane (-1: no receivers there); the
+  // padding planes have sponge factor 0 (they stay zero) and no receivers
+  std::vector<int32_t> rz(nz + kPadZ, -1);
+  if (w->fused_rec)
+    for (int l = 0; l < w->box.cnz; ++l) rz[w->box.z0 + l * w->box.sz] = l;
 
-  // tiling.  variant 0 selects the measured-best shape per storage type: 8
-  // wavefronts x 4 rows for float32, 8 x 2 rows for 16-bit storage (variant 3),
-  // whose lower register count fits two workgroups per CU.
-  if (p->variant == 0 && p->storage != WAVE_F32) w->p.variant = 3;
-  const Variant v = variant_info(w->p.variant);
-  const int TY = v.by * v.ry;
-  w->tiles_x = (nx + kTileX - 1) / kTileX;
-  w->tiles_y = (ny + TY - 1) / TY;
-  int zc = p->zchunk;
-  if (zc <= 0) {
-    // as many long-lived workgroups as fit on the 256 CUs at once: long
-    // z-chunks re-read fewer overlap planes and keep the prefetch pipeline full
-    const int per_plane = w->tiles_x * w->tiles_y;
-    const int want = 256 * step_blocks_per_cu(p->storage, w->p.variant);
-    const int chunks = std::max(1, (want + per_plane / 2) / per_plane);
-    zc = std::max(18, (nz + chunks - 1) / chunks);
-    zc = (zc + 8) / 9 * 9;  // the kernel advances nine planes per trip
-  }
-  w->zchunk = std::min(zc, nz);
-  w->nchunks = (nz + w->zchunk - 1) / w->zchunk;
-  w->total_tiles = w->tiles_x * w->tiles_y * w->nchunks;
+  // tiling: the forward step and (for adjoint contexts) the adjoint step
+  // each get a shape; variant 0 picks the measured-best ones
+  w->fwd = make_tiling(p, p->variant > 0 ? p->variant : auto_variant(p));
+  if (p->adjoint) w->adj = make_tiling(p, p->variant > 0 ? p->variant : kAdjointVariant);
 
   StepState init{};
   init.vmin_bits = 0x7f800000u;
@@ -392,12 +446,15 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   rc = hip_rc(hipMemcpyAsync(w->st, &init, sizeof(init), hipMemcpyHostToDevice, w->stream));
   if (!rc) rc = hip_rc(hipMemcpyAsync(w->gx, gx.data(), 4 * gx.size(), hipMemcpyHostToDevice, w->stream));
   if (!rc) rc = hip_rc(hipMemcpyAsync(w->gy, gy.data(), 4 * gy.size(), hipMemcpyHostToDevice, w->stream));
+  gz.resize(nz + kPadZ, 0.f);
   if (!rc) rc = hip_rc(hipMemcpyAsync(w->gz, gz.data(), 4 * gz.size(), hipMemcpyHostToDevice, w->stream));
+  if (!rc) rc = hip_rc(hipMemcpyAsync(w->rz, rz.data(), 4 * rz.size(), hipMemcpyHostToDevice, w->stream));
   if (!rc && p->nrec > 0) {
     rc = hip_rc(hipMemcpyAsync(w->rec_lin, lin.data(), 8 * lin.size(), hipMemcpyHostToDevice, w->stream));
     if (!rc) rc = hip_rc(hipMemcpyAsync(w->grec, grec.data(), 4 * grec.size(), hipMemcpyHostToDevice, w->stream));
   }
   if (!rc) rc = hip_rc(launch_init_m(vel_dev, w->m, w->N, static_cast<float>(p->dt), w->st, w->stream));
+  if (!rc) rc = hip_rc(launch_fill_zero(w->m + w->N, 4 * (w->Np - w->N), w->stream));
   if (!rc) rc = hip_rc(hipMemcpyAsync(&back, w->st, sizeof(back), hipMemcpyDeviceToHost, w->stream));
   if (!rc) rc = hip_rc(hipStreamSynchronize(w->stream));
   if (!rc && (back.flags & 2u)) rc = WAVE_EINVAL;  // non-finite or non-positive velocity
@@ -458,7 +515,7 @@ int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *re
   float *mu1 = reinterpret_cast<float *>(w->ws + L.mua);  // mu^{k+1}
   float *mu2 = reinterpret_cast<float *>(w->ws + L.mub);  // mu^{k+2}
   float *img = reinterpret_cast<float *>(w->ws + L.img);
-  auto slot = [&](int s) { return seg + static_cast<size_t>(s) * w->N; };
+  auto slot = [&](int s) { return seg + static_cast<size_t>(s) * w->Np; };
   const int nseg = (nt + K - 1) / K;
   w->drop_graphs();
 
@@ -472,15 +529,19 @@ int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *re
     rc = hip_rc(hipMemcpyAsync(ck, w->field(w->n & 1), fb, hipMemcpyDeviceToDevice, w->stream));
     if (!rc) rc = hip_rc(hipMemcpyAsync(ck + w->N, w->field((w->n & 1) ^ 1), fb, hipMemcpyDeviceToDevice, w->stream));
   }
-  if (!rc) rc = hip_rc(launch_fill_zero(mu1, fb, w->stream));
-  if (!rc) rc = hip_rc(launch_fill_zero(mu2, fb, w->stream));
-  if (!rc) rc = hip_rc(launch_fill_zero(img, fb, w->stream));
+  // padded fields start zero (their padding planes stay zero)
+  const size_t fbp = 4 * w->Np;
+  if (!rc) rc = hip_rc(launch_fill_zero(mu1, fbp, w->stream));
+  if (!rc) rc = hip_rc(launch_fill_zero(mu2, fbp, w->stream));
+  if (!rc) rc = hip_rc(launch_fill_zero(img, fbp, w->stream));
+  if (!rc) rc = hip_rc(launch_fill_zero(seg, fbp * (K + 2), w->stream));
 
   // 2) segments from last to first: recompute A^{jK+1..}, then adjoint steps
   for (int j = nseg - 1; j >= 0 && !rc; --j) {
     const int k_lo = j * K + 1, k_hi = std::min((j + 1) * K, nt);
     if (j == 0) {
-      rc = hip_rc(launch_fill_zero(slot(0), 2 * fb, w->stream));
+      rc = hip_rc(launch_fill_zero(slot(0), fb, w->stream));
+      if (!rc) rc = hip_rc(launch_fill_zero(slot(1), fb, w->stream));
     } else {
       const float *ck = ckpt + 2 * static_cast<size_t>(j - 1) * w->N;
       rc = hip_rc(hipMemcpyAsync(slot(1), ck, fb, hipMemcpyDeviceToDevice, w->stream));
@@ -488,16 +549,16 @@ int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *re
     }
     if (!rc) rc = hip_rc(launch_set_n(w->st, j * K, w->stream));
     // slot s holds A^{jK - 1 + s}
-    StepArgs a = base_args(w);
+    StepArgs a = base_args(w, w->fwd);
     a.wavelet = wavelet_dev;
     for (int k = 0; k < k_hi - j * K && !rc; ++k) {
       a.cur = slot(k + 1);
       a.prev = slot(k);
       a.out = slot(k + 2);
       a.k = k;
-      rc = hip_rc(launch_step(WAVE_F32, w->p.variant, false, a, w->stream));
+      rc = hip_rc(launch_step(WAVE_F32, w->fwd.variant, false, a, w->stream));
     }
-    StepArgs b = base_args(w);
+    StepArgs b = base_args(w, w->adj);
     b.sx = -1;
     b.img = img;
     b.resid = resid_dev;
@@ -508,7 +569,7 @@ int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *re
       b.out = mu2;  // mu^k overwrites mu^{k+2}
       b.fwd = slot(k - j * K + 1);
       b.resid_row = k - 1;
-      rc = hip_rc(launch_step(WAVE_F32, w->p.variant, true, b, w->stream));
+      rc = hip_rc(launch_step(WAVE_F32, w->adj.variant, true, b, w->stream));
       if (!rc && !w->fused_rec && w->p.nrec > 0)
         rc = hip_rc(launch_scatter(mu2, w->rec_lin, w->p.nrec, w->m, w->grec, resid_dev, k - 1, w->stream));
       std::swap(mu1, mu2);

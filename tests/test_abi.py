@@ -82,6 +82,15 @@ def test_workspace_bytes(lib):
     rc, badj = _bytes(lib, _params(lib, adjoint=1, nt_max=100))
     # 10 steps per checkpoint: 9 checkpoint pairs + 12 segment slots + 3 adjoint fields
     assert rc == 0 and badj - b32 >= 4 * N * (2 * 9 + 12 + 3)
+    # fields the step kernel touches carry 15 zero planes past nz
+    rc, b40 = _bytes(lib, _params(lib, nz=40))
+    assert rc == 0 and b40 - b32 >= 3 * 4 * 16 * 12 * 30
+
+
+def test_plane_size_limit(lib):
+    # at most 2^24 nodes per xy plane (buffer offsets of a z-chunk stay below 2^31 bytes)
+    assert _bytes(lib, _params(lib, nx=4096, ny=4096, nz=1))[0] == 0
+    assert _bytes(lib, _params(lib, nx=4097, ny=4096, nz=1))[0] == L.WAVE_EINVAL
 
 
 @pytest.mark.parametrize("kw", [

@@ -96,12 +96,34 @@ def test_tiling_variants_and_zchunks_are_bitwise_identical():
     so results must agree to the bit; an LDS race or halo bug breaks this."""
     from paper_2404_04441_amd import variant_count
 
+    from paper_2404_04441_amd._lib import WAVE_EINVAL, WaveError
+
+    # nx = 71: shapes with 2 or 4 x nodes per lane must refuse it (EINVAL)
     shape, h, vel, dt, nt, wav, rec, src, _ = ragged_case("box")
     base = gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05)
+    ran = 0
     for v in range(variant_count()):
         for zc in (0, 5, 16, 64):
-            _say(f"case: variant={v} zchunk={zc}")
-            got = gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05, variant=v, zchunk=zc)
+            _say(f"case: nx=71 variant={v} zchunk={zc}")
+            try:
+                got = gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05, variant=v, zchunk=zc)
+            except WaveError as e:
+                assert e.status == WAVE_EINVAL, (v, zc)
+                continue
+            ran += 1
+            assert np.array_equal(got["u"], base["u"]), (v, zc)
+            assert np.array_equal(got["traces"], base["traces"]), (v, zc)
+    assert ran >= 8 * 4
+    # nx = 68 (a multiple of 4, ragged against every tile width): every shape runs
+    vel2 = np.ascontiguousarray(vel[:, :, :68])
+    rec2 = plane_receivers(68, shape[1], 3)
+    base = gpu_run(vel2, h, dt, src, wav, rec2, nt, sponge_width=5, sponge_alpha=0.05)
+    ref2 = oracle.forward(vel2, h, dt, src, wav, rec2, nt=nt, sponge_width=5, sponge_alpha=0.05)
+    assert oracle.rel_l2(base["u"], ref2["u"]) <= TOL_F32 and oracle.rel_l2(base["traces"], ref2["traces"]) <= TOL_F32
+    for v in range(variant_count()):
+        for zc in (0, 16):
+            _say(f"case: nx=68 variant={v} zchunk={zc}")
+            got = gpu_run(vel2, h, dt, src, wav, rec2, nt, sponge_width=5, sponge_alpha=0.05, variant=v, zchunk=zc)
             assert np.array_equal(got["u"], base["u"]), (v, zc)
             assert np.array_equal(got["traces"], base["traces"]), (v, zc)
 

@@ -162,6 +162,70 @@ def precision_leg(nt: int = 500) -> dict:
     return out
 
 
+# Seconds for 1024^3 x 1000 steps printed in the paper's Table "cuda-time"
+# (NVIDIA GPUs, no thread-block clusters): context for the kernel study.
+PAPER_CUDA_TIME_S = {
+    "gmem": {"A100": 27.058, "GH200": 11.710},
+    "smem": {"A100": 23.740, "GH200": 11.635},
+    "st_reg_fixed": {"A100": 19.908, "GH200": 9.445},
+    "st_semi": {"A100": 16.154, "GH200": 9.654},
+}
+
+
+def kernel_study_leg(nt: int = 20) -> dict:
+    """The paper's kernel comparison rebuilt on one MI355X: its two 3D-blocking
+    designs (gmem, smem) and 2.5D streaming tile shapes, each the whole fused
+    float32 step, on the 1024^3 workload; the time for 1000 steps is 1000 x the
+    average step-kernel time.  Then the grid-size sweep of the automatic shape
+    (grid points per second against N, as in the paper's grid/s figure)."""
+    import torch
+
+    from paper_2404_04441_amd import Solver, variant_info
+    from synth import workload
+    from synth.velocity import smooth_random_torch
+    from synth.workloads import line_receivers
+
+    W = workload("precision")
+    dev = torch.device("cuda:0")
+    vel = smooth_random_torch(W.shape, seed=3, device=dev)
+    wav = torch.from_numpy(W.wavelet(max(nt, 50))).to(dev)
+    traces = torch.empty((max(nt, 50), len(W.rec)), dtype=torch.float32, device=dev)
+    kernels = {"gmem (3D blocks 64x4x4, global memory)": 14, "smem (3D blocks 64x4x4 + halo in LDS)": 15,
+               "2.5D 64x32, 1 node/lane, 3 planes in flight": 0, "2.5D 64x32, 1 node/lane, 1 plane in flight": 5,
+               "2.5D 256x8, 4 nodes/lane": 12, "2.5D 128x32, 2 nodes/lane (automatic at 1024^2 planes)": 11}
+    out = {"workload": f"{W.name}, float32, Dirichlet, {nt} timed steps per kernel",
+           "paper_seconds_1000_steps": PAPER_CUDA_TIME_S}
+    for name, v in kernels.items():
+        s = Solver(vel, W.h, W.dt, src=W.src, rec=W.rec, variant=v)
+        s.run(3, wav, traces)
+        r = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT["f32"])
+        r["variant"] = v
+        r["shape"] = variant_info(v)
+        r["seconds_1000_steps"] = round(r["kernel_ms"], 3)
+        s.close()
+        out[name] = r
+        print(f"[bench] kernel study {name}: {r}", file=sys.stderr, flush=True)
+    del vel
+    torch.cuda.empty_cache()
+    sweep, tuned = {}, {}
+    for n in (128, 256, 384, 512, 640, 768, 896, 1024):
+        v_n = smooth_random_torch((n, n, n), seed=3, device=dev)
+        rec = line_receivers(n, n // 2, 4)
+        tr = torch.empty((50, len(rec)), dtype=torch.float32, device=dev)
+        steps = 50 if n <= 512 else nt
+        for tune, dst in ((False, sweep), (True, tuned)):
+            s = Solver(v_n, W.h, W.dt, src=(n // 2, n // 2, n // 2), rec=rec, tune=tune)
+            s.run(3, wav, tr)
+            dst[str(n)] = kernel_rate(s, steps, wav, tr, n ** 3, BYTES_PER_POINT["f32"])["gpts_per_s"]
+            s.close()
+        del v_n
+        torch.cuda.empty_cache()
+    out["grid_sweep_gpts_per_s"] = sweep
+    out["grid_sweep_tuned_gpts_per_s"] = tuned
+    print(f"[bench] grid sweep: {sweep} tuned: {tuned}", file=sys.stderr, flush=True)
+    return out
+
+
 def gradient_leg() -> dict:
     """The 256^3 two-layer gradient workload (800 steps, sqrt(T) checkpoints):
     time of the velocity gradient against the time of the forward run."""
@@ -235,9 +299,11 @@ def main():
     ap.add_argument("--nt", type=int, default=0, help="time steps per shot (default: the workload's 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the 16-bit, 1024^3 and gradient measurements")
+                    help="skip the 16-bit, 1024^3, kernel-study and gradient measurements")
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the Poisson shot stream to serve after the throughput run (0: skip)")
+    ap.add_argument("--study-only", action="store_true",
+                    help="run only the 1024^3 kernel study (3D gmem/smem vs 2.5D shapes) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -254,6 +320,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.study_only:
+        print(json.dumps({"kernel_study_1024": kernel_study_leg()}), flush=True)
+        return
     dev = torch.device("cuda:0")
     W = workload("large")
     nt = args.nt or W.nt
@@ -337,6 +406,7 @@ def main():
         out["forms_512"] = storage_forms_leg(W, v_dev, min(nt, 200))
         del v_dev
         out["precision_1024"] = precision_leg()
+        out["kernel_study_1024"] = kernel_study_leg()
         out["gradient_256"] = gradient_leg()
         print(f"[bench] gradient: {out['gradient_256']}", file=sys.stderr, flush=True)
     if args.serving > 0:

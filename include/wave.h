@@ -81,12 +81,18 @@ typedef struct {
   int32_t adjoint;           /* nonzero: reserve the workspace wave_adjoint needs (float32 only) */
   int32_t nt_max;            /* adjoint: largest nt wave_adjoint will be called with */
   int32_t ckpt_interval;     /* adjoint: steps between checkpoints; 0 = ceil(sqrt(nt_max)) */
-  int32_t variant;           /* kernel tile shape, 1 .. wave_variant_count()-1; 0 = automatic (the
-                                measured-best shape for the storage type and nx); shapes with 2 or 4
-                                x nodes per lane need nx divisible by 2 or 4 (else WAVE_EINVAL) */
+  int32_t variant;           /* kernel variant, 1 .. wave_variant_count()-1 (see wave_variant_info);
+                                0 = automatic (the measured-best 2.5D shape for the storage type
+                                and nx).  WAVE_EINVAL: 2 or 4 x nodes per lane with nx not divisible
+                                by that; a 3D-blocked family with 16-bit storage or adjoint */
   int32_t zchunk;            /* z-planes per workgroup, rounded up to a multiple of 9 and capped so a
                                 workgroup's buffers span < 2 GiB; 0 = chosen from the grid size */
   int32_t graph_steps;       /* >0: replay steps from a captured HIP graph of this many steps */
+  int32_t tune;              /* 1 with variant = 0 and zchunk = 0: wave_create times the candidate
+                                2.5D shapes and z-chunks for a few steps on the fresh (zero) fields
+                                and keeps the fastest; the choice is cached per (nx, ny, nz,
+                                storage) for the life of the process.  Every choice computes the
+                                same bits.  0: the fixed automatic rule */
 } wave_params;
 
 /* Fill `p` with defaults: no source, no receivers, float32 storage,
@@ -164,6 +170,17 @@ int wave_destroy(wave_t w);
 
 /* Number of kernel tiling variants (valid values of wave_params.variant). */
 int wave_variant_count(void);
+
+/* Shape of kernel variant `variant` (0 .. wave_variant_count()-1), written to
+ * info[0..4] (caller-owned host array of 5): family, by, ry, pd, vec.
+ * Family 0 is the 2.5D blocking of paper Sec. IV-A (tile x and y, stream
+ * along z): tiles of 64*vec x by*ry nodes, pd planes of loads in flight.
+ * Families 1 and 2 are the paper's 3D-blocking designs of the same section
+ * ("gmem": every stencil value from global memory; "smem": a 3D tile with
+ * its halo staged in shared memory): blocks of 64 x by x ry nodes, float32
+ * storage and forward steps only.  Errors: WAVE_EINVAL for a null `info` or
+ * an out-of-range variant. */
+int wave_variant_info(int32_t variant, int32_t *info);
 
 /* Static text for a status code. */
 const char *wave_status_string(int status);

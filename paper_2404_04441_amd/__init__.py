@@ -10,7 +10,7 @@ from ._lib import WaveError, WaveParams, LIB_PATH, EXPORTS  # noqa: F401
 def __getattr__(name):
     # torch-dependent fronts are imported lazily so that the C-ABI checks work
     # without touching the GPU
-    if name in ("Solver", "variant_count"):
+    if name in ("Solver", "variant_count", "variant_info"):
         from . import solver
         return getattr(solver, name)
     if name == "WaveFn":

@@ -20,7 +20,7 @@ STORAGE = {"f32": WAVE_F32, "f16": WAVE_F16, "bf16": WAVE_BF16}
 EXPORTS = (
     "wave_params_init", "wave_workspace_bytes", "wave_create", "wave_reset", "wave_step", "wave_run",
     "wave_adjoint", "wave_read_field", "wave_time_index", "wave_sync_status", "wave_destroy",
-    "wave_variant_count", "wave_status_string",
+    "wave_variant_count", "wave_variant_info", "wave_status_string",
 )
 
 
@@ -41,6 +41,7 @@ class WaveParams(ctypes.Structure):
         ("variant", ctypes.c_int32),
         ("zchunk", ctypes.c_int32),
         ("graph_steps", ctypes.c_int32),
+        ("tune", ctypes.c_int32),
     ]
 
 
@@ -76,6 +77,7 @@ def lib():
         L.wave_sync_status.argtypes = [vp, P(u32)]
         L.wave_destroy.argtypes = [vp]
         L.wave_variant_count.argtypes = []
+        L.wave_variant_info.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.wave_status_string.argtypes = [ctypes.c_int]
         L.wave_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:

@@ -670,6 +670,153 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   }
 }
 
+// ------------------------------------------------------------ 3D-blocked kernels
+//
+// The two 3D-blocking designs the paper compares against 2.5D streaming
+// (Sec. IV-A: "gmem" reads every stencil point from global memory, "smem"
+// stages a 3D tile with its halo in shared memory), rebuilt for gfx950 with
+// the same fused update, sponge, source and receivers and the same
+// floating-point operation order as step_kernel, so their results are
+// bitwise identical to it.  Float32 storage, forward only.  A workgroup is a
+// 64 x BY x BZ block of nodes, one thread per node.
+
+// Byte offset of node (x, y, z) in a float32 field whose resource starts at
+// plane zlo, or kOOB outside the grid in x or y or below plane 0 (the
+// padding planes past nz read as zeros).
+__device__ __forceinline__ uint32_t node_off(int x, int y, int z, int nx, int ny, int zlo) {
+  const bool ok = x >= 0 && x < nx && y >= 0 && y < ny && z >= 0;
+  const uint32_t e = (static_cast<uint32_t>(z - zlo) * static_cast<uint32_t>(ny) + static_cast<uint32_t>(y)) *
+                         static_cast<uint32_t>(nx) +
+                     static_cast<uint32_t>(x);
+  return ok ? e * 4u : kOOB;
+}
+
+// Node of this thread and the shared set-up of the 3D kernels.
+template <int BY, int BZ>
+struct Block3D {
+  int x0, y0, z0, x, y, z, zlo;
+  bool inside;
+  __device__ bool init(const StepArgs &a) {
+    const int nwg = static_cast<int>(gridDim.x);
+    const int bid = static_cast<int>(blockIdx.x);
+    const int logical = (bid & 7) * (nwg >> 3) + (bid >> 3);
+    if (logical >= a.total_tiles) return false;
+    const int tix = logical % a.tiles_x;
+    const int rest = logical / a.tiles_x;
+    const int tiy = rest % a.tiles_y;
+    const int tiz = rest / a.tiles_y;
+    x0 = tix * kTileX;
+    y0 = tiy * BY;
+    z0 = tiz * BZ;
+    const int t = static_cast<int>(threadIdx.x);
+    x = x0 + (t & 63);
+    y = y0 + (t >> 6) % BY;
+    z = z0 + t / (64 * BY);
+    zlo = max(z0 - R, 0);
+    inside = x < a.nx && y < a.ny && z < a.nz;
+    return true;
+  }
+};
+
+// The fused update of one node from its Laplacian (float32 storage), with the
+// receiver sample; identical operations to step_kernel<kF32, ...>.
+__device__ __forceinline__ void update_node(const StepArgs &a, int n, int x, int y, int z, bool inside, float c,
+                                            float lap, float pc, float mc, float gzv, rsrc_t rO, uint32_t voff) {
+  const float gxv = inside ? a.gx[x] : 0.f;
+  const float gyv = inside ? a.gy[y] : 0.f;
+  const float g = gxv * (gyv * gzv);
+  const float wsrc = a.sx >= 0 ? a.wavelet[n] * a.src_scale : 0.f;
+  const float qsel = (a.sx >= 0 && x == a.sx && y == a.sy) ? 1.f : 0.f;
+  const float wsp = z == a.sz ? wsrc : 0.f;
+  float t = fmaf(-g, pc, 2.f * c);
+  t = fmaf(mc, lap, t);
+  t = fmaf(qsel, wsp, t);
+  const float v = t * g;
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rO, static_cast<int>(inside ? voff : kOOB), 0, kNT);
+  if (inside && a.box.cnx > 0 && z < a.nz && a.rz[z] >= 0) {
+    const int dx = x - a.box.x0, dy = y - a.box.y0;
+    if (dx >= 0 && dx % a.box.sx == 0 && dx / a.box.sx < a.box.cnx && dy >= 0 && dy % a.box.sy == 0 &&
+        dy / a.box.sy < a.box.cny)
+      a.traces[static_cast<size_t>(n) * a.nrec + (a.rz[z] * a.box.cny + dy / a.box.sy) * a.box.cnx + dx / a.box.sx] =
+          v;
+  }
+}
+
+// "gmem": every one of the 25 stencil values is a load of its own; reuse
+// between neighbouring threads is left to the L1 and L2 caches.
+template <int BY, int BZ>
+__global__ void __launch_bounds__(64 * BY * BZ) gmem_kernel(StepArgs a) {
+  Block3D<BY, BZ> b;
+  if (!b.init(a)) return;
+  const int nx = a.nx, ny = a.ny, n = a.st->n + a.k;
+  const uint32_t planes = static_cast<uint32_t>(b.z0 + BZ + R - b.zlo);
+  const uint32_t bytes = planes * static_cast<uint32_t>(nx) * static_cast<uint32_t>(ny) * 4u;
+  const size_t base = static_cast<size_t>(b.zlo) * nx * ny;
+  const rsrc_t rU = make_rsrc(static_cast<const float *>(a.cur) + base, bytes);
+  const rsrc_t rP = make_rsrc(static_cast<const float *>(a.prev) + base, bytes);
+  const rsrc_t rO = make_rsrc(static_cast<float *>(a.out) + base, bytes);
+  const rsrc_t rM = make_rsrc(a.m + base, bytes);
+  auto U = [&](int x, int y, int z) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rU, static_cast<int>(node_off(x, y, z, nx, ny, b.zlo)),
+                                                                0, 0));
+  };
+  const int x = b.x, y = b.y, z = b.z;
+  const uint32_t own = node_off(x, y, z, nx, ny, b.zlo);
+  const float c = U(x, y, z);
+  float lap = a.c.k0 * c;
+#pragma unroll
+  for (int m = 1; m <= R; ++m) {
+    lap = fmaf(a.c.kx[m - 1], U(x + m, y, z) + U(x - m, y, z), lap);
+    lap = fmaf(a.c.ky[m - 1], U(x, y + m, z) + U(x, y - m, z), lap);
+    lap = fmaf(a.c.kz[m - 1], U(x, y, z + m) + U(x, y, z - m), lap);
+  }
+  const float pc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rP, static_cast<int>(own), 0, kNT));
+  const float mc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rM, static_cast<int>(own), 0, kNT));
+  const float gzv = b.inside ? a.gz[z] : 0.f;
+  update_node(a, n, x, y, z, b.inside, c, lap, pc, mc, gzv, rO, own);
+}
+
+// "smem": the block's nodes and their radius-4 halo in all three directions
+// are staged in LDS, (64+8) x (BY+8) x (BZ+8) values, then every stencil value
+// is read from there.
+template <int BY, int BZ>
+__global__ void __launch_bounds__(64 * BY * BZ) smem_kernel(StepArgs a) {
+  constexpr int SX = kTileX + 2 * R, SY = BY + 2 * R, SZ = BZ + 2 * R;
+  __shared__ float T[SZ][SY][SX];
+  Block3D<BY, BZ> b;
+  if (!b.init(a)) return;
+  const int nx = a.nx, ny = a.ny, n = a.st->n + a.k;
+  const uint32_t planes = static_cast<uint32_t>(b.z0 + BZ + R - b.zlo);
+  const uint32_t bytes = planes * static_cast<uint32_t>(nx) * static_cast<uint32_t>(ny) * 4u;
+  const size_t base = static_cast<size_t>(b.zlo) * nx * ny;
+  const rsrc_t rU = make_rsrc(static_cast<const float *>(a.cur) + base, bytes);
+  const rsrc_t rP = make_rsrc(static_cast<const float *>(a.prev) + base, bytes);
+  const rsrc_t rO = make_rsrc(static_cast<float *>(a.out) + base, bytes);
+  const rsrc_t rM = make_rsrc(a.m + base, bytes);
+  for (int i = static_cast<int>(threadIdx.x); i < SX * SY * SZ; i += 64 * BY * BZ) {
+    const int lx = i % SX, ly = (i / SX) % SY, lz = i / (SX * SY);
+    const uint32_t off = node_off(b.x0 - R + lx, b.y0 - R + ly, b.z0 - R + lz, nx, ny, b.zlo);
+    T[lz][ly][lx] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rU, static_cast<int>(off), 0, 0));
+  }
+  __syncthreads();
+  const int tx = static_cast<int>(threadIdx.x) & 63, ty = (static_cast<int>(threadIdx.x) >> 6) % BY,
+            tz = static_cast<int>(threadIdx.x) / (64 * BY);
+  const int cx = tx + R, cy = ty + R, cz = tz + R;
+  const float c = T[cz][cy][cx];
+  float lap = a.c.k0 * c;
+#pragma unroll
+  for (int m = 1; m <= R; ++m) {
+    lap = fmaf(a.c.kx[m - 1], T[cz][cy][cx + m] + T[cz][cy][cx - m], lap);
+    lap = fmaf(a.c.ky[m - 1], T[cz][cy + m][cx] + T[cz][cy - m][cx], lap);
+    lap = fmaf(a.c.kz[m - 1], T[cz + m][cy][cx] + T[cz - m][cy][cx], lap);
+  }
+  const uint32_t own = node_off(b.x, b.y, b.z, nx, ny, b.zlo);
+  const float pc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rP, static_cast<int>(own), 0, kNT));
+  const float mc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rM, static_cast<int>(own), 0, kNT));
+  const float gzv = b.inside ? a.gz[b.z] : 0.f;
+  update_node(a, n, b.x, b.y, b.z, b.inside, c, lap, pc, mc, gzv, rO, own);
+}
+
 // ------------------------------------------------------------ utilities
 
 __global__ void init_m_kernel(const float *__restrict__ vel, float *__restrict__ m, size_t n, float dt,
@@ -813,25 +960,29 @@ unsigned grid_for(size_t n, unsigned block) {
   return static_cast<unsigned>(want < 1 ? 1 : (want > cap ? cap : want));
 }
 
-// Tile shapes (BY, RY, PD, VEC) of the step kernel; variant 0 is also the
-// shape the runtime's automatic choice falls back to.
-#define WAVE_VARIANTS(X) \
-  X(0, 8, 4, 3, 1)       \
-  X(1, 4, 8, 1, 1)       \
-  X(2, 4, 4, 3, 1)       \
-  X(3, 8, 2, 3, 1)       \
-  X(4, 4, 4, 1, 1)       \
-  X(5, 8, 4, 1, 1)       \
-  X(6, 2, 8, 1, 1)       \
-  X(7, 4, 2, 3, 1)       \
-  X(8, 8, 2, 3, 2)       \
-  X(9, 8, 2, 1, 4)       \
-  X(10, 4, 4, 1, 2)      \
-  X(11, 8, 4, 1, 2)      \
-  X(12, 8, 1, 3, 4)      \
-  X(13, 4, 2, 3, 2)
+// Kernel variants (FAMILY, BY, RY, PD, VEC).  Family 0 is the 2.5D streaming
+// step_kernel (tile 64*VEC x BY*RY, PD planes in flight); variant 0 is also
+// the shape the runtime's automatic choice falls back to.  Families 1 (gmem)
+// and 2 (smem) are the 3D-blocked kernels with blocks of 64 x BY x RY nodes.
+#define WAVE_VARIANTS(X)  \
+  X(0, 0, 8, 4, 3, 1)     \
+  X(1, 0, 4, 8, 1, 1)     \
+  X(2, 0, 4, 4, 3, 1)     \
+  X(3, 0, 8, 2, 3, 1)     \
+  X(4, 0, 4, 4, 1, 1)     \
+  X(5, 0, 8, 4, 1, 1)     \
+  X(6, 0, 2, 8, 1, 1)     \
+  X(7, 0, 4, 2, 3, 1)     \
+  X(8, 0, 8, 2, 3, 2)     \
+  X(9, 0, 8, 2, 1, 4)     \
+  X(10, 0, 4, 4, 1, 2)    \
+  X(11, 0, 8, 4, 1, 2)    \
+  X(12, 0, 8, 1, 3, 4)    \
+  X(13, 0, 4, 2, 3, 2)    \
+  X(14, 1, 4, 4, 1, 1)    \
+  X(15, 2, 4, 4, 1, 1)
 
-#define WAVE_VARIANT_INFO(id, by, ry, pd, vec) {by, ry, pd, vec},
+#define WAVE_VARIANT_INFO(id, fam, by, ry, pd, vec) {by, ry, pd, vec, fam},
 constexpr Variant kVariants[] = {WAVE_VARIANTS(WAVE_VARIANT_INFO)};
 #undef WAVE_VARIANT_INFO
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -845,29 +996,43 @@ int blocks_per_cu() {
   return nb > 0 ? nb : 1;
 }
 
+template <int FAM, int S, int BY, int RY, int PD, int VEC, bool ADJ>
+int blocks_fam() {
+  if constexpr (FAM == 0) return blocks_per_cu<S, BY, RY, PD, VEC, ADJ>();
+  return 1;  // the 3D-blocked kernels size their grids from the block shape alone
+}
+
 template <int S, bool ADJ>
 int blocks_variant(int v) {
   switch (v) {
-#define WAVE_VARIANT_CASE(id, by, ry, pd, vec) \
-  case id: return blocks_per_cu<S, by, ry, pd, vec, ADJ>();
+#define WAVE_VARIANT_CASE(id, fam, by, ry, pd, vec) \
+  case id: return blocks_fam<fam, S, by, ry, pd, vec, ADJ>();
     WAVE_VARIANTS(WAVE_VARIANT_CASE)
 #undef WAVE_VARIANT_CASE
     default: return 1;
   }
 }
 
-template <int S, int BY, int RY, int PD, int VEC, bool ADJ>
+template <int FAM, int S, int BY, int RY, int PD, int VEC, bool ADJ>
 hipError_t launch_one(const StepArgs &a, hipStream_t s) {
   const unsigned grid = static_cast<unsigned>((a.total_tiles + 7) / 8 * 8);
-  hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, ADJ>), dim3(grid), dim3(64 * BY), 0, s, a);
+  if constexpr (FAM == 0) {
+    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, ADJ>), dim3(grid), dim3(64 * BY), 0, s, a);
+  } else if constexpr (S != kF32 || ADJ) {
+    return hipErrorInvalidValue;  // the 3D-blocked kernels are float32 forward only
+  } else if constexpr (FAM == 1) {
+    hipLaunchKernelGGL((gmem_kernel<BY, RY>), dim3(grid), dim3(64 * BY * RY), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((smem_kernel<BY, RY>), dim3(grid), dim3(64 * BY * RY), 0, s, a);
+  }
   return hipGetLastError();
 }
 
 template <int S, bool ADJ>
 hipError_t launch_variant(int v, const StepArgs &a, hipStream_t s) {
   switch (v) {
-#define WAVE_VARIANT_CASE(id, by, ry, pd, vec) \
-  case id: return launch_one<S, by, ry, pd, vec, ADJ>(a, s);
+#define WAVE_VARIANT_CASE(id, fam, by, ry, pd, vec) \
+  case id: return launch_one<fam, S, by, ry, pd, vec, ADJ>(a, s);
     WAVE_VARIANTS(WAVE_VARIANT_CASE)
 #undef WAVE_VARIANT_CASE
     default: return hipErrorInvalidValue;

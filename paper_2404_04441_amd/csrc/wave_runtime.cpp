@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -51,9 +52,15 @@ int validate(const wave_params *p) {
     if (p->storage != WAVE_F32 || p->nt_max < 1 || p->ckpt_interval < 0) return WAVE_EINVAL;
   }
   if (p->variant < 0 || p->variant >= variant_count()) return WAVE_EINVAL;
-  // an explicit tile shape with VEC > 1 x nodes per lane needs whole vectors per row
-  if (p->variant > 0 && p->nx % variant_info(p->variant).vec) return WAVE_EINVAL;
+  if (p->variant > 0) {
+    const Variant v = variant_info(p->variant);
+    // a tile shape with VEC > 1 x nodes per lane needs whole vectors per row
+    if (p->nx % v.vec) return WAVE_EINVAL;
+    // the 3D-blocked kernels are float32 forward only
+    if (v.family != 0 && (p->storage != WAVE_F32 || p->adjoint)) return WAVE_EINVAL;
+  }
   if (p->zchunk < 0 || p->graph_steps < 0) return WAVE_EINVAL;
+  if (p->tune < 0 || p->tune > 1) return WAVE_EINVAL;
   return WAVE_OK;
 }
 
@@ -155,14 +162,22 @@ int auto_variant(const wave_params *p) {
   return p->storage == WAVE_F32 ? 0 : 3;
 }
 // The adjoint kernel keeps two z queues: its default is a one-node-per-lane
-// shape that fits in registers (8 wavefronts x 2 rows).
-constexpr int kAdjointVariant = 3;
+// shape that fits in registers (8 wavefronts x 4 rows, one plane in flight).
+constexpr int kAdjointVariant = 5;
 
 Tiling make_tiling(const wave_params *p, int variant) {
   const int nx = p->nx, ny = p->ny, nz = p->nz;
   Tiling t;
   t.variant = variant;
   const Variant v = variant_info(variant);
+  if (v.family != 0) {  // 3D blocks of 64 x by x ry nodes
+    t.tiles_x = (nx + kTileX - 1) / kTileX;
+    t.tiles_y = (ny + v.by - 1) / v.by;
+    t.zchunk = v.ry;
+    t.nchunks = (nz + v.ry - 1) / v.ry;
+    t.total_tiles = t.tiles_x * t.tiles_y * t.nchunks;
+    return t;
+  }
   const int TY = v.by * v.ry;
   const int TX = kTileX * v.vec;
   t.tiles_x = (nx + TX - 1) / TX;
@@ -351,6 +366,73 @@ int do_reset(wave_ctx *w) {
   return rc;
 }
 
+// ---- shape tuning: time each candidate (2.5D shape, z-chunk) for a few
+// steps on the zeroed fields and keep the fastest.  All candidates compute
+// identical bits, so the choice only changes speed.
+struct TuneEntry {
+  int nx, ny, nz, storage;
+  Tiling t;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune_cache;
+
+int tune_forward(wave_ctx *w) {
+  const wave_params &p = w->p;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const TuneEntry &e : g_tune_cache)
+      if (e.nx == p.nx && e.ny == p.ny && e.nz == p.nz && e.storage == p.storage) {
+        w->fwd = e.t;
+        return WAVE_OK;
+      }
+  }
+  std::vector<Tiling> cands;
+  for (int v = 0; v < variant_count(); ++v) {
+    const Variant info = variant_info(v);
+    if (info.family != 0 || p.nx % info.vec) continue;
+    wave_params q = p;
+    q.variant = v;
+    q.zchunk = 0;
+    cands.push_back(make_tiling(&q, v));
+    for (int zc : {27, 45, 72, 99, 135, 198, 270}) {
+      q.zchunk = zc;
+      const Tiling t = make_tiling(&q, v);
+      if (zc < p.nz && t.zchunk != cands.back().zchunk) cands.push_back(t);
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = hip_rc(hipEventCreate(&e0));
+  if (!rc) rc = hip_rc(hipEventCreate(&e1));
+  // no source while timing (the wavelet is not known yet); the fields stay zero
+  const int src_x = w->p.src[0];
+  w->p.src[0] = -1;
+  Tiling best = w->fwd;
+  float best_ms = 3.0e38f;
+  for (size_t i = 0; i < cands.size() && !rc; ++i) {
+    w->fwd = cands[i];
+    rc = enqueue_steps(w, 1, nullptr, nullptr, false);
+    if (!rc) rc = hip_rc(hipEventRecord(e0, w->stream));
+    if (!rc) rc = enqueue_steps(w, 3, nullptr, nullptr, false);
+    if (!rc) rc = hip_rc(hipEventRecord(e1, w->stream));
+    if (!rc) rc = hip_rc(hipEventSynchronize(e1));
+    float ms = 0.f;
+    if (!rc) rc = hip_rc(hipEventElapsedTime(&ms, e0, e1));
+    if (!rc && ms < best_ms) {
+      best_ms = ms;
+      best = cands[i];
+    }
+  }
+  w->p.src[0] = src_x;
+  w->fwd = best;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (!rc) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache.push_back(TuneEntry{p.nx, p.ny, p.nz, p.storage, best});
+  }
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -470,6 +552,7 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
     const double k0 = kC[0] * (ix2 + iy2 + iz2);
     w->gamma = static_cast<float>(Mmax * (std::fabs(k0) + kabs));
   }
+  if (!rc && p->tune && p->variant == 0 && p->zchunk == 0) rc = tune_forward(w);
   if (!rc) rc = do_reset(w);
   if (rc) {
     delete w;
@@ -618,6 +701,17 @@ int wave_destroy(wave_t w) {
 }
 
 int wave_variant_count(void) { return variant_count(); }
+
+int wave_variant_info(int32_t variant, int32_t *info) {
+  if (!info || variant < 0 || variant >= variant_count()) return WAVE_EINVAL;
+  const Variant v = variant_info(variant);
+  info[0] = v.family;
+  info[1] = v.by;
+  info[2] = v.ry;
+  info[3] = v.pd;
+  info[4] = v.vec;
+  return WAVE_OK;
+}
 
 const char *wave_status_string(int status) {
   switch (status) {

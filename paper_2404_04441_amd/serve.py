@@ -191,13 +191,14 @@ def summarize(results: Dict[int, ShotResult], requests: List[ShotRequest], elaps
 class GpuBackend:
     """Runs each shot on its own stream through libwave (one Solver per shot)."""
 
-    def __init__(self, device=None, graph_steps: int = 20, variant: int = 0):
+    def __init__(self, device=None, graph_steps: int = 20, variant: int = 0, tune: bool = True):
         import torch
 
         self.torch = torch
         self.device = device or torch.device("cuda", torch.cuda.current_device())
         self.graph_steps = graph_steps
         self.variant = variant
+        self.tune = tune  # time the tile shapes once per grid shape (libwave caches the choice)
 
     def footprint(self, req: ShotRequest) -> int:
         import ctypes
@@ -238,7 +239,7 @@ class GpuBackend:
             traces = torch.empty((req.nt, len(req.rec)), dtype=torch.float32, device=self.device)
             s = Solver(vel, req.h, req.dt, src=req.src, rec=req.rec, sponge_width=req.sponge_width,
                        sponge_alpha=req.sponge_alpha, storage=req.storage, variant=self.variant,
-                       graph_steps=self.graph_steps, stream=stream)
+                       graph_steps=self.graph_steps, tune=self.tune and self.variant == 0, stream=stream)
             del vel  # m now lives in the workspace
         return {"solver": s, "stream": stream, "wav": wav, "traces": traces}
 

@@ -34,11 +34,13 @@ class Solver:
     storage  : "f32", "f16" or "bf16" wavefield storage
     adjoint  : reserve the adjoint workspace for runs up to ``nt_max`` steps
     variant, zchunk, graph_steps : kernel tiling / replay options
+    tune : time the candidate tile shapes at create and keep the fastest (cached per grid shape)
     """
 
     def __init__(self, vel: torch.Tensor, h, dt: float, src=None, rec=None, sponge_width: int = 0,
                  sponge_alpha: float = 0.015, storage: str = "f32", adjoint: bool = False, nt_max: int = 0,
-                 ckpt_interval: int = 0, variant: int = 0, zchunk: int = 0, graph_steps: int = 0, stream=None):
+                 ckpt_interval: int = 0, variant: int = 0, zchunk: int = 0, graph_steps: int = 0, tune: bool = False,
+                 stream=None):
         lib = L.lib()
         _dev_f32(vel, "vel")
         nz, ny, nx = vel.shape
@@ -58,6 +60,7 @@ class Solver:
         p.rec = self._rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if p.nrec else None
         p.adjoint, p.nt_max, p.ckpt_interval = int(bool(adjoint)), int(nt_max), int(ckpt_interval)
         p.variant, p.zchunk, p.graph_steps = int(variant), int(zchunk), int(graph_steps)
+        p.tune = 1 if tune else 0
         nbytes = ctypes.c_size_t()
         L.check(lib.wave_workspace_bytes(ctypes.byref(p), ctypes.byref(nbytes)), "wave_workspace_bytes")
         self.workspace_bytes = nbytes.value
@@ -168,3 +171,11 @@ class Solver:
 
 def variant_count() -> int:
     return int(L.lib().wave_variant_count())
+
+
+def variant_info(variant: int) -> dict:
+    """Shape of a kernel variant: family (0 = 2.5D streaming, 1 = 3D gmem,
+    2 = 3D smem), by, ry, pd, vec."""
+    info = (ctypes.c_int32 * 5)()
+    L.check(L.lib().wave_variant_info(int(variant), info), "wave_variant_info")
+    return dict(zip(("family", "by", "ry", "pd", "vec"), (int(v) for v in info)))

@@ -97,7 +97,7 @@ def test_plane_size_limit(lib):
     dict(nx=0), dict(nz=-1), dict(dt=0.0), dict(dx=float("nan")), dict(storage=3),
     dict(src=(16, 0, 0)), dict(src=(0, -1, 0)), dict(sponge_width=-1), dict(sponge_alpha=-0.1),
     dict(adjoint=1, nt_max=0), dict(adjoint=1, nt_max=10, storage=L.WAVE_F16), dict(variant=99),
-    dict(zchunk=-2), dict(graph_steps=-1),
+    dict(zchunk=-2), dict(graph_steps=-1), dict(tune=2),
 ])
 def test_invalid_params_rejected(lib, kw):
     rc, _ = _bytes(lib, _params(lib, **kw))
@@ -145,3 +145,27 @@ def test_status_strings_and_variants(lib):
         assert L.status_string(code)
     assert L.status_string(-77) == "unknown status"
     assert lib.wave_variant_count() >= 1
+
+
+def test_variant_info_and_shape_validation(lib):
+    n = lib.wave_variant_count()
+    info = (ctypes.c_int32 * 5)()
+    families = set()
+    for v in range(n):
+        assert lib.wave_variant_info(v, info) == 0
+        fam, by, ry, pd, vec = list(info)
+        families.add(fam)
+        assert fam in (0, 1, 2) and by >= 1 and ry >= 1 and pd >= 1 and vec in (1, 2, 4)
+        if fam == 0:
+            assert 9 % pd == 0 and 8 * ry <= 64
+        # nx = 16 accepts every lane width; nx = 18 (even, not a multiple of 4) rejects vec 4
+        assert _bytes(lib, _params(lib, variant=v, nx=16))[0] == 0
+        assert (_bytes(lib, _params(lib, variant=v, nx=18))[0] == 0) == (vec != 4)
+        # the 3D-blocked families are float32 forward only
+        rc16 = _bytes(lib, _params(lib, variant=v, nx=16, storage=L.WAVE_F16))[0]
+        rcadj = _bytes(lib, _params(lib, variant=v, nx=16, adjoint=1, nt_max=10))[0]
+        assert (rc16 == 0) == (fam == 0) and (rcadj == 0) == (fam == 0)
+    assert families == {0, 1, 2}
+    assert lib.wave_variant_info(n, info) == L.WAVE_EINVAL
+    assert lib.wave_variant_info(-1, info) == L.WAVE_EINVAL
+    assert lib.wave_variant_info(0, None) == L.WAVE_EINVAL

@@ -174,7 +174,8 @@ PAPER_CUDA_TIME_S = {
 
 def kernel_study_leg(nt: int = 20) -> dict:
     """The paper's kernel comparison rebuilt on one MI355X: its two 3D-blocking
-    designs (gmem, smem) and 2.5D streaming tile shapes, each the whole fused
+    designs (gmem, smem), 2.5D streaming tile shapes and the 2.5D semi-stencil
+    form (st_semi), each the whole fused
     float32 step, on the 1024^3 workload; the time for 1000 steps is 1000 x the
     average step-kernel time.  Then the grid-size sweep of the automatic shape
     (grid points per second against N, as in the paper's grid/s figure)."""
@@ -192,7 +193,8 @@ def kernel_study_leg(nt: int = 20) -> dict:
     traces = torch.empty((max(nt, 50), len(W.rec)), dtype=torch.float32, device=dev)
     kernels = {"gmem (3D blocks 64x4x4, global memory)": 14, "smem (3D blocks 64x4x4 + halo in LDS)": 15,
                "2.5D 64x32, 1 node/lane, 3 planes in flight": 0, "2.5D 64x32, 1 node/lane, 1 plane in flight": 5,
-               "2.5D 256x8, 4 nodes/lane": 12, "2.5D 128x32, 2 nodes/lane (automatic at 1024^2 planes)": 11}
+               "2.5D 256x8, 4 nodes/lane": 12, "2.5D 128x32, 2 nodes/lane (automatic at 1024^2 planes)": 11,
+               "2.5D semi-stencil 64x32, 1 node/lane": 16, "2.5D semi-stencil 256x8, 4 nodes/lane": 17}
     out = {"workload": f"{W.name}, float32, Dirichlet, {nt} timed steps per kernel",
            "paper_seconds_1000_steps": PAPER_CUDA_TIME_S}
     for name, v in kernels.items():

@@ -83,8 +83,9 @@ struct Variant {
   int ry;   // consecutive rows per wavefront (tile height = by * ry)
   int pd;   // z-planes of loads in flight ahead of the plane being computed
   int vec;  // consecutive x nodes per lane (tile width = 64 * vec); needs nx % vec == 0
-  int family;  // 0: 2.5D streaming; 1: 3D blocks from global memory; 2: 3D blocks via LDS
-               // (families 1 and 2: blocks of 64 x by x ry nodes, float32 forward only)
+  int family;  // 0: 2.5D streaming; 1: 3D blocks from global memory; 2: 3D blocks via LDS;
+               // 3: 2.5D streaming with a semi-stencil z sum (families 1 and 2: blocks of
+               // 64 x by x ry nodes; families 1-3: float32 forward only)
 };
 
 int variant_count();

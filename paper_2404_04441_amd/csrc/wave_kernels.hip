@@ -236,7 +236,11 @@ static_assert(kPadZ >= (kQ - 1) + kMaxPD + R, "z padding must cover the last tri
 // flight ahead of the plane being computed (PD divides 9: the z loop is
 // unrolled 9 times so the queue rotates by register renaming instead of
 // copies).  VEC > 1 requires nx % VEC == 0 (whole rows stay aligned).
-template <int S, int BY, int RY, int PD, int VEC, bool ADJ>
+// SEMI: the z part of the stencil as a semi-stencil (the paper's st_semi,
+// Sec. IV-A): the left half sum_m kz_m A(z-m) of plane z is summed R planes
+// early, at the position of plane z-R (from planes z-R .. z-1), so only planes
+// z .. z+R stay live in the queue; the right half is added when z is computed.
+template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ>
 __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   using C = Codec<S>;
   using StageT = Stage<S, RY, VEC, (2 * R + BY - 1) / BY, ADJ>;
@@ -251,6 +255,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   static_assert(kQ % PD == 0, "pipeline depth must divide the queue length");
   static_assert(PD <= kMaxPD, "z padding assumes at most kMaxPD planes in flight");
   static_assert(VEC == 1 || VEC == 2 || VEC == 4, "lane width");
+  static_assert(!(SEMI && ADJ), "the semi-stencil form is forward only");
   // each LDS plane ends with a scratch row: halo writes of lanes or
   // wavefronts with nothing to write go there, so no write is predicated
   constexpr int LP = LH * LW + 64 * VEC;
@@ -475,6 +480,21 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       }
     }
   }
+  // semi-stencil partials: slot (p - zb + R) mod 9 holds sum_m kz_m A(p-m) of plane p
+  float X[SEMI ? kQ : 1][RY][VEC];
+  if constexpr (SEMI) {
+#pragma unroll
+    for (int k = R; k < 2 * R; ++k)
+#pragma unroll
+      for (int j = 0; j < RY; ++j)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+          float t = a.c.kz[R - 1] * q[k - R][j][i];
+#pragma unroll
+          for (int m = R - 1; m >= 1; --m) t = fmaf(a.c.kz[m - 1], q[k - m][j][i], t);
+          X[k][j][i] = t;
+        }
+  }
   StageT stg[PD];
 #pragma unroll
   for (int s = 0; s < PD; ++s) load_stage(stg[s], zb + s);
@@ -486,8 +506,8 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   // neighbours from the queue Q, x neighbours from a window of the LDS row,
   // y neighbours from this lane's own rows when they lie in the strip, else
   // from the LDS rows above and below.
-  auto laplacian = [&](const float (&Q)[kQ][RY][VEC], const float *Lp, int cs, int s0, int j, float *lap)
-      __attribute__((always_inline)) {
+  auto laplacian = [&](const float (&Q)[kQ][RY][VEC], const float *Lp, int cs, int s0, int j, float *lap,
+                       const float (&Xp)[SEMI ? kQ : 1][RY][VEC]) __attribute__((always_inline)) {
     const float *row = Lp + (R + w * RY + j) * LW + VEC * lane;  // window start: column x - R
     float win[VEC + 2 * R];
 #pragma unroll
@@ -517,7 +537,17 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       for (int i = 0; i < VEC; ++i) {
         lap[i] = fmaf(a.c.kx[m - 1], win[R + i + m] + win[R + i - m], lap[i]);
         lap[i] = fmaf(a.c.ky[m - 1], yp[i] + ym[i], lap[i]);
-        lap[i] = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i] + Q[(s0 + R - m + kQ) % kQ][j][i], lap[i]);
+        if constexpr (!SEMI)
+          lap[i] = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i] + Q[(s0 + R - m + kQ) % kQ][j][i], lap[i]);
+      }
+    }
+    if constexpr (SEMI) {  // left half from the partial, right half from the queue
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) {
+        float t = Xp[cs][j][i];
+#pragma unroll
+        for (int m = 1; m <= R; ++m) t = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i], t);
+        lap[i] += t;
       }
     }
   };
@@ -539,6 +569,15 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) q[(s + 2 * R) % kQ][j][i] = row_get<S>(cs.lead[j], i) * inv_cur;
         lds_put<VEC>(L + (R + w * RY + j) * LW + R + VEC * lane, q[cslot][j]);
+        if constexpr (SEMI) {  // left half of plane z+R from planes z .. z+R-1
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) {
+            float t = a.c.kz[R - 1] * q[cslot][j][i];
+#pragma unroll
+            for (int m = R - 1; m >= 1; --m) t = fmaf(a.c.kz[m - 1], q[(s + 2 * R - m) % kQ][j][i], t);
+            X[(s + 2 * R) % kQ][j][i] = t;
+          }
+        }
         if constexpr (ADJ) {
 #pragma unroll
           for (int i = 0; i < VEC; ++i) qF[(s + 2 * R) % kQ][j][i] = __uint_as_float(cs.leadF[j].w[i]);
@@ -583,7 +622,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
         float lap[VEC];
-        laplacian(q, L, cslot, s, j, lap);
+        laplacian(q, L, cslot, s, j, lap, X);
         const float gyz = gyv[j] * gzv;
         float v[VEC], vv[VEC];
 #pragma unroll
@@ -627,7 +666,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
         }
         if constexpr (ADJ) {
           float lapF[VEC], im[VEC];
-          laplacian(qF, LF, cslot, s, j, lapF);
+          laplacian(qF, LF, cslot, s, j, lapF, X);
 #pragma unroll
           for (int i = 0; i < VEC; ++i) im[i] = fmaf(q[cslot][j][i], lapF[i], ic[j][i]);
           st_words<NF, kNT>(row_put<kF32, VEC>(im), rI, vrow_f[j], sz0f);
@@ -963,7 +1002,8 @@ unsigned grid_for(size_t n, unsigned block) {
 // Kernel variants (FAMILY, BY, RY, PD, VEC).  Family 0 is the 2.5D streaming
 // step_kernel (tile 64*VEC x BY*RY, PD planes in flight); variant 0 is also
 // the shape the runtime's automatic choice falls back to.  Families 1 (gmem)
-// and 2 (smem) are the 3D-blocked kernels with blocks of 64 x BY x RY nodes.
+// and 2 (smem) are the 3D-blocked kernels with blocks of 64 x BY x RY nodes;
+// family 3 is the 2.5D kernel with the semi-stencil z sum.
 #define WAVE_VARIANTS(X)  \
   X(0, 0, 8, 4, 3, 1)     \
   X(1, 0, 4, 8, 1, 1)     \
@@ -980,25 +1020,29 @@ unsigned grid_for(size_t n, unsigned block) {
   X(12, 0, 8, 1, 3, 4)    \
   X(13, 0, 4, 2, 3, 2)    \
   X(14, 1, 4, 4, 1, 1)    \
-  X(15, 2, 4, 4, 1, 1)
+  X(15, 2, 4, 4, 1, 1)    \
+  X(16, 3, 8, 4, 3, 1)    \
+  X(17, 3, 8, 1, 3, 4)
 
 #define WAVE_VARIANT_INFO(id, fam, by, ry, pd, vec) {by, ry, pd, vec, fam},
 constexpr Variant kVariants[] = {WAVE_VARIANTS(WAVE_VARIANT_INFO)};
 #undef WAVE_VARIANT_INFO
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <int S, int BY, int RY, int PD, int VEC, bool ADJ>
+template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ>
 int blocks_per_cu() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void *>(step_kernel<S, BY, RY, PD, VEC, ADJ>), 64 * BY, 0) != hipSuccess)
+          &nb, reinterpret_cast<const void *>(step_kernel<S, BY, RY, PD, VEC, SEMI, ADJ>), 64 * BY, 0) !=
+      hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
 template <int FAM, int S, int BY, int RY, int PD, int VEC, bool ADJ>
 int blocks_fam() {
-  if constexpr (FAM == 0) return blocks_per_cu<S, BY, RY, PD, VEC, ADJ>();
+  if constexpr (FAM == 0) return blocks_per_cu<S, BY, RY, PD, VEC, false, ADJ>();
+  if constexpr (FAM == 3 && S == kF32 && !ADJ) return blocks_per_cu<S, BY, RY, PD, VEC, true, false>();
   return 1;  // the 3D-blocked kernels size their grids from the block shape alone
 }
 
@@ -1017,9 +1061,11 @@ template <int FAM, int S, int BY, int RY, int PD, int VEC, bool ADJ>
 hipError_t launch_one(const StepArgs &a, hipStream_t s) {
   const unsigned grid = static_cast<unsigned>((a.total_tiles + 7) / 8 * 8);
   if constexpr (FAM == 0) {
-    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, ADJ>), dim3(grid), dim3(64 * BY), 0, s, a);
+    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, ADJ>), dim3(grid), dim3(64 * BY), 0, s, a);
   } else if constexpr (S != kF32 || ADJ) {
-    return hipErrorInvalidValue;  // the 3D-blocked kernels are float32 forward only
+    return hipErrorInvalidValue;  // the study families are float32 forward only
+  } else if constexpr (FAM == 3) {
+    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, true, false>), dim3(grid), dim3(64 * BY), 0, s, a);
   } else if constexpr (FAM == 1) {
     hipLaunchKernelGGL((gmem_kernel<BY, RY>), dim3(grid), dim3(64 * BY * RY), 0, s, a);
   } else {

@@ -56,7 +56,7 @@ int validate(const wave_params *p) {
     const Variant v = variant_info(p->variant);
     // a tile shape with VEC > 1 x nodes per lane needs whole vectors per row
     if (p->nx % v.vec) return WAVE_EINVAL;
-    // the 3D-blocked kernels are float32 forward only
+    // the study families (3D-blocked, semi-stencil) are float32 forward only
     if (v.family != 0 && (p->storage != WAVE_F32 || p->adjoint)) return WAVE_EINVAL;
   }
   if (p->zchunk < 0 || p->graph_steps < 0) return WAVE_EINVAL;
@@ -170,7 +170,7 @@ Tiling make_tiling(const wave_params *p, int variant) {
   Tiling t;
   t.variant = variant;
   const Variant v = variant_info(variant);
-  if (v.family != 0) {  // 3D blocks of 64 x by x ry nodes
+  if (v.family == 1 || v.family == 2) {  // 3D blocks of 64 x by x ry nodes
     t.tiles_x = (nx + kTileX - 1) / kTileX;
     t.tiles_y = (ny + v.by - 1) / v.by;
     t.zchunk = v.ry;

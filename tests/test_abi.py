@@ -155,17 +155,17 @@ def test_variant_info_and_shape_validation(lib):
         assert lib.wave_variant_info(v, info) == 0
         fam, by, ry, pd, vec = list(info)
         families.add(fam)
-        assert fam in (0, 1, 2) and by >= 1 and ry >= 1 and pd >= 1 and vec in (1, 2, 4)
-        if fam == 0:
+        assert fam in (0, 1, 2, 3) and by >= 1 and ry >= 1 and pd >= 1 and vec in (1, 2, 4)
+        if fam in (0, 3):
             assert 9 % pd == 0 and 8 * ry <= 64
         # nx = 16 accepts every lane width; nx = 18 (even, not a multiple of 4) rejects vec 4
         assert _bytes(lib, _params(lib, variant=v, nx=16))[0] == 0
         assert (_bytes(lib, _params(lib, variant=v, nx=18))[0] == 0) == (vec != 4)
-        # the 3D-blocked families are float32 forward only
+        # the study families (3D-blocked, semi-stencil) are float32 forward only
         rc16 = _bytes(lib, _params(lib, variant=v, nx=16, storage=L.WAVE_F16))[0]
         rcadj = _bytes(lib, _params(lib, variant=v, nx=16, adjoint=1, nt_max=10))[0]
         assert (rc16 == 0) == (fam == 0) and (rcadj == 0) == (fam == 0)
-    assert families == {0, 1, 2}
+    assert families == {0, 1, 2, 3}
     assert lib.wave_variant_info(n, info) == L.WAVE_EINVAL
     assert lib.wave_variant_info(-1, info) == L.WAVE_EINVAL
     assert lib.wave_variant_info(0, None) == L.WAVE_EINVAL

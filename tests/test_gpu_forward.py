@@ -98,8 +98,9 @@ def test_tiling_variants_and_zchunks_are_bitwise_identical():
     from paper_2404_04441_amd._lib import WAVE_EINVAL, WaveError
 
     # nx = 71: shapes with 2 or 4 x nodes per lane must refuse it (EINVAL); the
-    # 3D-blocked families (gmem, smem) run the same operations per node
-    shape, h, vel, dt, nt, wav, rec, src, _ = ragged_case("box")
+    # 3D-blocked families (gmem, smem) run the same operations per node; the
+    # semi-stencil family sums z in another order (checked against the oracle)
+    shape, h, vel, dt, nt, wav, rec, src, ref = ragged_case("box")
     base = gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05)
     for v in range(variant_count()):
         info = variant_info(v)
@@ -111,6 +112,10 @@ def test_tiling_variants_and_zchunks_are_bitwise_identical():
                 assert e.value.status == WAVE_EINVAL
                 continue
             got = gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05, variant=v, zchunk=zc)
+            if info["family"] == 3:
+                assert oracle.rel_l2(got["u"], ref["u"]) <= TOL_F32, (v, zc)
+                assert oracle.rel_l2(got["traces"], ref["traces"]) <= TOL_F32, (v, zc)
+                continue
             assert np.array_equal(got["u"], base["u"]), (v, zc)
             assert np.array_equal(got["traces"], base["traces"]), (v, zc)
     # nx = 68 (a multiple of 4, ragged against every tile width): every shape runs
@@ -123,6 +128,10 @@ def test_tiling_variants_and_zchunks_are_bitwise_identical():
         for zc in (0, 16):
             _say(f"case: nx=68 variant={v} zchunk={zc}")
             got = gpu_run(vel2, h, dt, src, wav, rec2, nt, sponge_width=5, sponge_alpha=0.05, variant=v, zchunk=zc)
+            if variant_info(v)["family"] == 3:
+                assert oracle.rel_l2(got["u"], ref2["u"]) <= TOL_F32, (v, zc)
+                assert oracle.rel_l2(got["traces"], ref2["traces"]) <= TOL_F32, (v, zc)
+                continue
             assert np.array_equal(got["u"], base["u"]), (v, zc)
             assert np.array_equal(got["traces"], base["traces"]), (v, zc)
 

@@ -26,6 +26,10 @@ What each module follows:
   constant-velocity Green's function, dense brute-force operator).
 * ``storage`` -- 16-bit wavefield storage with power-of-two scaling
   (the paper is silent on precision; parity unpinned, see module header).
+* ``cpml`` -- the CPML absorbing boundary (the paper's boundary, cited in
+  Sec. II / IV-A without formulas; the formulation is a reading, see its
+  header), pinned by textbook weights, the undamped limit and absorption
+  against a large-domain reference.
 """
 from .coefficients import fd_coefficients, second_derivative_weights
 from .operators import laplacian, sponge_profile, sponge_field, stability_courant, symbol_peak
@@ -37,6 +41,7 @@ from .dense import dense_laplacian
 from .metrics import rel_l2, rel_max
 from .pointwise import step_at
 from . import storage
+from . import cpml
 
 __all__ = [
     "fd_coefficients", "second_derivative_weights", "laplacian", "sponge_profile", "sponge_field",

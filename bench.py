@@ -137,6 +137,26 @@ def storage_forms_leg(W, vel_dev, nt: int) -> dict:
     return out
 
 
+def cpml_leg(W, vel_dev, nt: int) -> dict:
+    """The 512^3 workload with CPML layers of 20 nodes (the paper's boundary)
+    instead of the sponge: time per step of the whole step (memory-variable
+    update, fused step, boundary correction, receiver gather), float32."""
+    import torch
+
+    from paper_2404_04441_amd import Solver
+
+    wav = torch.from_numpy(W.wavelet(nt)).to(vel_dev.device)
+    traces = torch.empty((nt, len(W.rec)), dtype=torch.float32, device=vel_dev.device)
+    s = Solver(vel_dev, W.h, W.dt, src=W.src, rec=W.rec, cpml_width=W.sponge_width, cpml_f0=W.f0)
+    s.run(10, wav, traces)
+    r = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT["f32"])
+    s.close()
+    r = {"step_ms": r["kernel_ms"], "gpts_per_s": r["gpts_per_s"],
+         "note": "all kernels of a step; roofline fraction at 16 B/pt for comparison", "roofline_frac": r["roofline_frac"],
+         "layers": W.sponge_width, "reflection": 1e-3, "f0_hz": W.f0}
+    return r
+
+
 def precision_leg(nt: int = 500) -> dict:
     """The 1024^3 workload (smooth random model, 500 steps) in each storage type."""
     import torch
@@ -301,7 +321,7 @@ def main():
     ap.add_argument("--nt", type=int, default=0, help="time steps per shot (default: the workload's 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the 16-bit, 1024^3, kernel-study and gradient measurements")
+                    help="skip the 16-bit, CPML, 1024^3, kernel-study and gradient measurements")
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the Poisson shot stream to serve after the throughput run (0: skip)")
     ap.add_argument("--study-only", action="store_true",
@@ -406,6 +426,8 @@ def main():
     if not args.no_forms:
         v_dev = torch.from_numpy(vel).to(dev)
         out["forms_512"] = storage_forms_leg(W, v_dev, min(nt, 200))
+        out["cpml_512"] = cpml_leg(W, v_dev, min(nt, 200))
+        print(f"[bench] cpml: {out['cpml_512']}", file=sys.stderr, flush=True)
         del v_dev
         out["precision_1024"] = precision_leg()
         out["kernel_study_1024"] = kernel_study_leg()

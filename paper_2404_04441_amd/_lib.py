@@ -42,6 +42,9 @@ class WaveParams(ctypes.Structure):
         ("zchunk", ctypes.c_int32),
         ("graph_steps", ctypes.c_int32),
         ("tune", ctypes.c_int32),
+        ("cpml_width", ctypes.c_int32),
+        ("cpml_reflection", ctypes.c_double),
+        ("cpml_f0", ctypes.c_double),
     ]
 
 

@@ -78,6 +78,20 @@ struct StepArgs {
   int resid_row;      // row of resid injected by this launch
 };
 
+// CPML boundary (float32 forward): memory variables psi_a, zeta_a in slab
+// arrays over the W-node layers of each axis -- x: [nz][ny][2W], y:
+// [nz][2W][nx], z: [2W][ny][nx]; slab index s = i for i < W and
+// i - (n - 2W) for i >= n - W.
+struct CpmlArgs {
+  float *psi[3], *zeta[3];   // x, y, z
+  const float *ca[3];        // a coefficient per node along each axis (n_a entries)
+  const float *cb[3];        // b coefficient
+  float d1w[3][4];           // w_m / h_a (first derivative)
+  float d2w[3][5];           // c_m / h_a^2 (second derivative, c_0 first)
+  int W;                     // layer width in nodes (2W <= every axis)
+  int nx, ny, nz;
+};
+
 struct Variant {
   int by;   // wavefronts per workgroup
   int ry;   // consecutive rows per wavefront (tile height = by * ry)
@@ -112,5 +126,10 @@ hipError_t launch_check_finite(int storage, const void *field, size_t n, StepSta
 hipError_t launch_grad_final(const float *img, const float *m, float dt, float *grad, size_t n,
                              hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// psi_a^n = b psi_a^{n-1} + a D1_a cur, on the W-node layers
+hipError_t launch_cpml_psi(const CpmlArgs &c, const float *cur, hipStream_t s);
+// out += m * sum_a (D1_a psi_a + zeta_a), zeta_a = b zeta_a + a (D2_a cur + D1_a psi_a),
+// on the nodes within W + R of a face
+hipError_t launch_cpml_fix(const CpmlArgs &c, const float *cur, const float *m, float *out, hipStream_t s);
 
 }  // namespace wave

@@ -856,6 +856,153 @@ __global__ void __launch_bounds__(64 * BY * BZ) smem_kernel(StepArgs a) {
   update_node(a, n, b.x, b.y, b.z, b.inside, c, lap, pc, mc, gzv, rO, own);
 }
 
+// ------------------------------------------------------------ CPML boundary
+//
+// The convolutional PML the paper names as its boundary (Sec. II, Sec.
+// IV-A), for the second-order acoustic equation: per axis a memory variable
+// psi_a of the first derivative and zeta_a of the second,
+//   psi_a^n  = b psi_a^{n-1}  + a D1_a p^n
+//   zeta_a^n = b zeta_a^{n-1} + a (D2_a p^n + D1_a psi_a^n)
+//   p^{n+1}  = (plain leapfrog step) + m sum_a (D1_a psi_a^n + zeta_a^n).
+// Both kernels run one thread per node of the boundary shell: the planes of
+// the z layers, then the rows of the y layers in the remaining planes, then
+// the columns of the x layers in the remaining rows (each node once).
+
+// Node of shell index t for layers of E nodes (E <= n_a / 2 on every axis).
+__device__ __forceinline__ bool shell_node(long long t, int E, int nx, int ny, int nz, int &x, int &y, int &z) {
+  const int cz = min(2 * E, nz), cy = min(2 * E, ny), cx = min(2 * E, nx);
+  const long long plane = static_cast<long long>(nx) * ny;
+  const long long n1 = static_cast<long long>(cz) * plane;
+  if (t < n1) {
+    const int k = static_cast<int>(t / plane);
+    const long long r = t % plane;
+    z = k < E ? k : nz - cz + k;
+    y = static_cast<int>(r / nx);
+    x = static_cast<int>(r % nx);
+    return true;
+  }
+  t -= n1;
+  const int mz = nz - cz;
+  const long long n2 = static_cast<long long>(mz) * cy * nx;
+  if (t < n2) {
+    const long long row = static_cast<long long>(cy) * nx;
+    z = E + static_cast<int>(t / row);
+    const long long r = t % row;
+    const int k = static_cast<int>(r / nx);
+    y = k < E ? k : ny - cy + k;
+    x = static_cast<int>(r % nx);
+    return true;
+  }
+  t -= n2;
+  const int my = ny - cy;
+  const long long n3 = static_cast<long long>(mz) * my * cx;
+  if (t < n3) {
+    const long long per = static_cast<long long>(my) * cx;
+    z = E + static_cast<int>(t / per);
+    const long long r = t % per;
+    y = E + static_cast<int>(r / cx);
+    const int k = static_cast<int>(r % cx);
+    x = k < E ? k : nx - cx + k;
+    return true;
+  }
+  return false;
+}
+
+__host__ __device__ __forceinline__ long long shell_count(int E, int nx, int ny, int nz) {
+  const int cz = nz < 2 * E ? nz : 2 * E, cy = ny < 2 * E ? ny : 2 * E, cx = nx < 2 * E ? nx : 2 * E;
+  return static_cast<long long>(cz) * ny * nx + static_cast<long long>(nz - cz) * cy * nx +
+         static_cast<long long>(nz - cz) * (ny - cy) * cx;
+}
+
+// Slab index along an axis of n nodes with layers of W nodes, or -1.
+__device__ __forceinline__ int slab_index(int i, int n, int W) {
+  if (i < 0 || i >= n) return -1;
+  if (i < W) return i;
+  if (i >= n - W) return i - (n - 2 * W);
+  return -1;
+}
+
+// Offset of (x, y, z) with slab index s along axis a in that axis' slab array.
+__device__ __forceinline__ size_t slab_off(int a, int s, int x, int y, int z, const CpmlArgs &c) {
+  const size_t W2 = static_cast<size_t>(2 * c.W);
+  if (a == 0) return (static_cast<size_t>(z) * c.ny + y) * W2 + s;
+  if (a == 1) return (static_cast<size_t>(z) * W2 + s) * c.nx + x;
+  return (static_cast<size_t>(s) * c.ny + y) * c.nx + x;
+}
+
+// Value of a [nz][ny][nx] field at (x, y, z) shifted by k along axis a; zero
+// outside the grid.
+__device__ __forceinline__ float field_at(const float *f, int a, int k, int x, int y, int z, int nx, int ny, int nz) {
+  int xx = x, yy = y, zz = z;
+  if (a == 0) xx += k;
+  else if (a == 1) yy += k;
+  else zz += k;
+  if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) return 0.f;
+  return f[(static_cast<size_t>(zz) * ny + yy) * nx + xx];
+}
+
+__device__ __forceinline__ float psi_at(const CpmlArgs &c, int a, int k, int x, int y, int z) {
+  const int n = a == 0 ? c.nx : (a == 1 ? c.ny : c.nz);
+  const int i = (a == 0 ? x : (a == 1 ? y : z)) + k;
+  const int s = slab_index(i, n, c.W);
+  if (s < 0) return 0.f;
+  return c.psi[a][slab_off(a, s, a == 0 ? i : x, a == 1 ? i : y, a == 2 ? i : z, c)];
+}
+
+__global__ void cpml_psi_kernel(CpmlArgs c, const float *__restrict__ cur, long long count) {
+  const long long t = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
+  int x, y, z;
+  if (t >= count || !shell_node(t, c.W, c.nx, c.ny, c.nz, x, y, z)) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int i = a == 0 ? x : (a == 1 ? y : z);
+    const int n = a == 0 ? c.nx : (a == 1 ? c.ny : c.nz);
+    const int s = slab_index(i, n, c.W);
+    if (s < 0) continue;
+    float d = 0.f;
+#pragma unroll
+    for (int m = 1; m <= R; ++m)
+      d = fmaf(c.d1w[a][m - 1],
+               field_at(cur, a, m, x, y, z, c.nx, c.ny, c.nz) - field_at(cur, a, -m, x, y, z, c.nx, c.ny, c.nz), d);
+    float *ps = c.psi[a] + slab_off(a, s, x, y, z, c);
+    *ps = fmaf(c.cb[a][i], *ps, c.ca[a][i] * d);
+  }
+}
+
+__global__ void cpml_fix_kernel(CpmlArgs c, const float *__restrict__ cur, const float *__restrict__ m,
+                                float *out, long long count) {
+  const long long t = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
+  int x, y, z;
+  if (t >= count || !shell_node(t, c.W + R, c.nx, c.ny, c.nz, x, y, z)) return;
+  float extra = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int i = a == 0 ? x : (a == 1 ? y : z);
+    const int n = a == 0 ? c.nx : (a == 1 ? c.ny : c.nz);
+    if (i >= c.W + R && i < n - c.W - R) continue;  // psi_a and zeta_a vanish this far in
+    float dpsi = 0.f;
+#pragma unroll
+    for (int k = 1; k <= R; ++k)
+      dpsi = fmaf(c.d1w[a][k - 1], psi_at(c, a, k, x, y, z) - psi_at(c, a, -k, x, y, z), dpsi);
+    const int s = slab_index(i, n, c.W);
+    if (s < 0) {
+      extra += dpsi;
+      continue;
+    }
+    float d2 = c.d2w[a][0] * field_at(cur, a, 0, x, y, z, c.nx, c.ny, c.nz);
+#pragma unroll
+    for (int k = 1; k <= R; ++k)
+      d2 = fmaf(c.d2w[a][k],
+                field_at(cur, a, k, x, y, z, c.nx, c.ny, c.nz) + field_at(cur, a, -k, x, y, z, c.nx, c.ny, c.nz), d2);
+    float *ze = c.zeta[a] + slab_off(a, s, x, y, z, c);
+    const float zn = fmaf(c.cb[a][i], *ze, c.ca[a][i] * (d2 + dpsi));
+    *ze = zn;
+    extra += dpsi + zn;
+  }
+  const size_t o = (static_cast<size_t>(z) * c.ny + y) * c.nx + x;
+  out[o] = fmaf(m[o], extra, out[o]);
+}
+
 // ------------------------------------------------------------ utilities
 
 __global__ void init_m_kernel(const float *__restrict__ vel, float *__restrict__ m, size_t n, float dt,
@@ -1198,6 +1345,21 @@ hipError_t launch_check_finite(int storage, const void *field, size_t n, StepSta
 
 hipError_t launch_grad_final(const float *img, const float *m, float dt, float *grad, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(grad_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, img, m, dt, grad, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cpml_psi(const CpmlArgs &c, const float *cur, hipStream_t s) {
+  const long long n = shell_count(c.W, c.nx, c.ny, c.nz);
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cpml_psi_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, c, cur, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cpml_fix(const CpmlArgs &c, const float *cur, const float *m, float *out, hipStream_t s) {
+  const long long n = shell_count(c.W + kRadius, c.nx, c.ny, c.nz);
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cpml_fix_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, c, cur, m, out,
+                     n);
   return hipGetLastError();
 }
 

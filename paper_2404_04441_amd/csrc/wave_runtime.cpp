@@ -20,11 +20,15 @@ namespace {
 // Centred second-derivative weights, 8th order (Eq. 1 of paper Sec. II; the
 // paper leaves the values unprinted): the textbook values of Fornberg (1988).
 constexpr double kC[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+// Centred first-derivative weights, 8th order (the CPML memory variables):
+// f'(0) ~ sum_m w_m (f(m) - f(-m)), Fornberg (1988).
+constexpr double kD1[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct Layout {
-  size_t st, gx, gy, gz, rz, rec_lin, grec, m, fa, fb, fv, ckpt, seg, mua, mub, img, total;
+  size_t st, gx, gy, gz, rz, rec_lin, grec, m, fa, fb, fv, ckpt, seg, mua, mub, img;
+  size_t cpml_ab, cpml_slab[3], total;  // CPML: a/b tables, psi+zeta slab pair per axis
   int K, nck;
 };
 
@@ -38,6 +42,14 @@ int validate(const wave_params *p) {
   if (static_cast<int64_t>(p->nx) * p->ny > (int64_t(1) << 24)) return WAVE_EINVAL;
   if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dz) || !finite_pos(p->dt)) return WAVE_EINVAL;
   if (p->sponge_width < 0 || !std::isfinite(p->sponge_alpha) || p->sponge_alpha < 0.0) return WAVE_EINVAL;
+  if (p->cpml_width < 0) return WAVE_EINVAL;
+  if (p->cpml_width > 0) {
+    const int W = p->cpml_width;
+    if (p->sponge_width != 0 || p->storage != WAVE_F32 || p->adjoint) return WAVE_EINVAL;
+    if (2 * W > p->nx || 2 * W > p->ny || 2 * W > p->nz) return WAVE_EINVAL;
+    if (!(p->cpml_reflection > 0.0 && p->cpml_reflection <= 1.0)) return WAVE_EINVAL;
+    if (!std::isfinite(p->cpml_f0) || p->cpml_f0 < 0.0) return WAVE_EINVAL;
+  }
   if (p->storage < WAVE_F32 || p->storage > WAVE_BF16) return WAVE_EINVAL;
   if (p->src[0] >= 0) {
     if (p->src[0] >= p->nx || p->src[1] < 0 || p->src[1] >= p->ny || p->src[2] < 0 || p->src[2] >= p->nz)
@@ -104,6 +116,16 @@ int plan(const wave_params *p, Layout *L) {
     L->mua = take(4 * Np);
     L->mub = take(4 * Np);
     L->img = take(4 * Np);
+  }
+  L->cpml_ab = off;
+  L->cpml_slab[0] = L->cpml_slab[1] = L->cpml_slab[2] = off;
+  if (p->cpml_width > 0) {
+    const size_t W2 = 2 * static_cast<size_t>(p->cpml_width);
+    const size_t nx = p->nx, ny = p->ny, nz = p->nz;
+    L->cpml_ab = take(4 * 2 * (nx + ny + nz));
+    L->cpml_slab[0] = take(4 * 2 * nz * ny * W2);
+    L->cpml_slab[1] = take(4 * 2 * nz * W2 * nx);
+    L->cpml_slab[2] = take(4 * 2 * W2 * ny * nx);
   }
   L->total = off;
   return WAVE_OK;
@@ -221,6 +243,8 @@ struct wave_ctx {
   StepState *st = nullptr;
   float *gx = nullptr, *gy = nullptr, *gz = nullptr, *m = nullptr, *grec = nullptr;
   int32_t *rz = nullptr;
+  bool cpml = false;
+  CpmlArgs cp{};
   int64_t *rec_lin = nullptr;
   void *fa = nullptr, *fb = nullptr, *fv = nullptr;
   size_t N = 0;   // interior nodes
@@ -283,7 +307,8 @@ int enqueue_steps(wave_ctx *w, int count, const float *wavelet, float *traces, b
   StepArgs a = base_args(w, w->fwd);
   a.wavelet = wavelet;
   a.traces = traces;
-  if (sample && w->fused_rec) a.box = w->box;
+  // with CPML the receivers are sampled after the boundary correction
+  if (sample && w->fused_rec && !w->cpml) a.box = w->box;
   for (int k = 0; k < count; ++k) {
     const int parity = (w->n + k) & 1;
     a.cur = w->field(parity);
@@ -291,9 +316,14 @@ int enqueue_steps(wave_ctx *w, int count, const float *wavelet, float *traces, b
     a.prev = w->p.storage == WAVE_F32 ? w->field(parity ^ 1) : w->fv;
     a.vout = w->fv;
     a.k = k;
-    int rc = hip_rc(launch_step(w->p.storage, w->fwd.variant, false, a, w->stream));
+    int rc = 0;
+    if (w->cpml) rc = hip_rc(launch_cpml_psi(w->cp, static_cast<const float *>(a.cur), w->stream));
+    if (!rc) rc = hip_rc(launch_step(w->p.storage, w->fwd.variant, false, a, w->stream));
+    if (!rc && w->cpml)
+      rc = hip_rc(launch_cpml_fix(w->cp, static_cast<const float *>(a.cur), w->m, static_cast<float *>(a.out),
+                                  w->stream));
     if (rc) return rc;
-    if (sample && !w->fused_rec && w->p.nrec > 0) {
+    if (sample && (!w->fused_rec || w->cpml) && w->p.nrec > 0) {
       rc = hip_rc(launch_gather(w->p.storage, a.out, w->rec_lin, w->p.nrec, traces, w->st, k, w->stream));
       if (rc) return rc;
     }
@@ -356,9 +386,19 @@ int do_step(wave_ctx *w, int nsteps, const float *wavelet, float *traces) {
   return WAVE_OK;
 }
 
+// Bytes of the psi + zeta pair of axis a's CPML slabs.
+size_t slab_bytes(const wave_ctx *w, int a) {
+  const size_t W2 = 2 * static_cast<size_t>(w->p.cpml_width);
+  const size_t nx = w->p.nx, ny = w->p.ny, nz = w->p.nz;
+  const size_t n = a == 0 ? nz * ny * W2 : (a == 1 ? nz * W2 * nx : W2 * ny * nx);
+  return 4 * 2 * n;
+}
+
 int do_reset(wave_ctx *w) {
   const size_t es = w->p.storage == WAVE_F32 ? 4 : 2;
   int rc = hip_rc(launch_fill_zero(w->fa, es * w->Np, w->stream));
+  for (int a = 0; a < 3 && w->cpml && !rc; ++a)
+    rc = hip_rc(launch_fill_zero(w->ws + w->L.cpml_slab[a], slab_bytes(w, a), w->stream));
   if (!rc) rc = hip_rc(launch_fill_zero(w->fb, es * w->Np, w->stream));
   if (!rc && w->fv) rc = hip_rc(launch_fill_zero(w->fv, es * w->Np, w->stream));
   if (!rc) rc = hip_rc(launch_reset_state(w->st, w->stream));
@@ -433,6 +473,48 @@ int tune_forward(wave_ctx *w) {
   return rc;
 }
 
+// CPML profiles along each axis (FP64 on the host): depth xi into a layer of
+// W nodes, d = d0 xi^2 with d0 = -3 v_max ln(R) / (2 W h), alpha = pi f0 (1 - xi),
+// b = exp(-(d + alpha) dt), a = d (b - 1) / (d + alpha) (0 where d = 0).
+int setup_cpml(wave_ctx *w, float vmax) {
+  const wave_params &p = w->p;
+  const int W = p.cpml_width;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  const double h[3] = {p.dx, p.dy, p.dz};
+  const double pi = 3.14159265358979323846;
+  std::vector<float> tab(2 * static_cast<size_t>(p.nx + p.ny + p.nz));
+  float *dst_a = tab.data(), *dst_b = tab.data() + (p.nx + p.ny + p.nz);
+  float *base_a = reinterpret_cast<float *>(w->ws + w->L.cpml_ab);
+  float *base_b = base_a + (p.nx + p.ny + p.nz);
+  CpmlArgs &c = w->cp;
+  size_t off = 0;
+  for (int ax = 0; ax < 3; ++ax) {
+    const double d0 = -3.0 * vmax * std::log(p.cpml_reflection) / (2.0 * W * h[ax]);
+    for (int i = 0; i < n[ax]; ++i) {
+      const double xi = std::max(std::max(W - i, i - (n[ax] - 1 - W)), 0) / static_cast<double>(W);
+      const double d = d0 * xi * xi, alpha = pi * p.cpml_f0 * (1.0 - xi);
+      const double b = std::exp(-(d + alpha) * p.dt);
+      dst_a[off + i] = static_cast<float>(d > 0.0 ? d * (b - 1.0) / (d + alpha) : 0.0);
+      dst_b[off + i] = static_cast<float>(b);
+    }
+    c.ca[ax] = base_a + off;
+    c.cb[ax] = base_b + off;
+    off += n[ax];
+    for (int m = 0; m < 4; ++m) c.d1w[ax][m] = static_cast<float>(kD1[m] / h[ax]);
+    for (int m = 0; m < 5; ++m) c.d2w[ax][m] = static_cast<float>(kC[m] / (h[ax] * h[ax]));
+    c.psi[ax] = reinterpret_cast<float *>(w->ws + w->L.cpml_slab[ax]);
+    c.zeta[ax] = c.psi[ax] + slab_bytes(w, ax) / 8;
+  }
+  c.W = W;
+  c.nx = p.nx;
+  c.ny = p.ny;
+  c.nz = p.nz;
+  w->cpml = true;
+  int rc = hip_rc(hipMemcpyAsync(base_a, tab.data(), 4 * tab.size(), hipMemcpyHostToDevice, w->stream));
+  if (!rc) rc = hip_rc(hipStreamSynchronize(w->stream));
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -443,6 +525,7 @@ void wave_params_init(wave_params *p) {
   p->dx = p->dy = p->dz = 1.0;
   p->dt = 1.0;
   p->sponge_alpha = 0.015;
+  p->cpml_reflection = 1e-3;
   p->storage = WAVE_F32;
   p->src[0] = -1;
 }
@@ -551,8 +634,12 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
     for (int m = 1; m <= 4; ++m) kabs += 2.0 * std::fabs(kC[m]) * (ix2 + iy2 + iz2);
     const double k0 = kC[0] * (ix2 + iy2 + iz2);
     w->gamma = static_cast<float>(Mmax * (std::fabs(k0) + kabs));
+    if (!rc && p->cpml_width > 0) rc = setup_cpml(w, vmax);
   }
-  if (!rc && p->tune && p->variant == 0 && p->zchunk == 0) rc = tune_forward(w);
+  if (!rc && p->tune && p->variant == 0 && p->zchunk == 0) {
+    rc = do_reset(w);  // zero fields (and CPML memory) for the timing runs
+    if (!rc) rc = tune_forward(w);
+  }
   if (!rc) rc = do_reset(w);
   if (rc) {
     delete w;

@@ -87,6 +87,16 @@ def test_workspace_bytes(lib):
     assert rc == 0 and b40 - b32 >= 3 * 4 * 16 * 12 * 30
 
 
+def test_cpml_workspace(lib):
+    # psi and zeta slabs of W nodes per face pair on each axis (grid 16 x 12 x 10)
+    rc, b0 = _bytes(lib, _params(lib))
+    rc1, b1 = _bytes(lib, _params(lib, cpml_width=3))
+    assert rc == 0 and rc1 == 0
+    W2 = 6
+    slabs = 4 * 2 * (10 * 12 * W2 + 10 * W2 * 16 + W2 * 12 * 16)
+    assert b1 - b0 >= slabs + 4 * 2 * (16 + 12 + 10)
+
+
 def test_plane_size_limit(lib):
     # at most 2^24 nodes per xy plane (buffer offsets of a z-chunk stay below 2^31 bytes)
     assert _bytes(lib, _params(lib, nx=4096, ny=4096, nz=1))[0] == 0
@@ -98,6 +108,9 @@ def test_plane_size_limit(lib):
     dict(src=(16, 0, 0)), dict(src=(0, -1, 0)), dict(sponge_width=-1), dict(sponge_alpha=-0.1),
     dict(adjoint=1, nt_max=0), dict(adjoint=1, nt_max=10, storage=L.WAVE_F16), dict(variant=99),
     dict(zchunk=-2), dict(graph_steps=-1), dict(tune=2),
+    dict(cpml_width=-1), dict(cpml_width=3, sponge_width=2), dict(cpml_width=3, storage=L.WAVE_F16),
+    dict(cpml_width=3, adjoint=1, nt_max=10), dict(cpml_width=6), dict(cpml_width=3, cpml_reflection=0.0),
+    dict(cpml_width=3, cpml_reflection=1.5), dict(cpml_width=3, cpml_f0=-1.0),
 ])
 def test_invalid_params_rejected(lib, kw):
     rc, _ = _bytes(lib, _params(lib, **kw))

@@ -95,7 +95,8 @@ typedef struct {
                                 same bits.  0: the fixed automatic rule */
   int32_t cpml_width;        /* >0: CPML absorbing layers of this many nodes on all six faces (the
                                 boundary of paper Sec. II / IV-A; float32, forward only, needs
-                                sponge_width = 0 and 2*cpml_width <= nx, ny, nz); 0: none */
+                                sponge_width = 0, 2*cpml_width <= nx, ny, nz and nx*ny*nz < 2^31);
+                                0: none */
   double cpml_reflection;    /* CPML target reflection coefficient R in (0, 1] (default 1e-3):
                                 d(xi) = -3 v_max ln(R) xi^2 / (2 W h) */
   double cpml_f0;            /* CPML frequency shift alpha(xi) = pi f0 (1 - xi), Hz (default 0) */

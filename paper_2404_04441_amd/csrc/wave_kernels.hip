@@ -868,51 +868,50 @@ __global__ void __launch_bounds__(64 * BY * BZ) smem_kernel(StepArgs a) {
 // the z layers, then the rows of the y layers in the remaining planes, then
 // the columns of the x layers in the remaining rows (each node once).
 
-// Node of shell index t for layers of E nodes (E <= n_a / 2 on every axis).
-__device__ __forceinline__ bool shell_node(long long t, int E, int nx, int ny, int nz, int &x, int &y, int &z) {
-  const int cz = min(2 * E, nz), cy = min(2 * E, ny), cx = min(2 * E, nx);
-  const long long plane = static_cast<long long>(nx) * ny;
-  const long long n1 = static_cast<long long>(cz) * plane;
-  if (t < n1) {
-    const int k = static_cast<int>(t / plane);
-    const long long r = t % plane;
-    z = k < E ? k : nz - cz + k;
-    y = static_cast<int>(r / nx);
-    x = static_cast<int>(r % nx);
-    return true;
+// Node t of the boundary shell for layers of E nodes: the planes of the z
+// layers, then in the remaining planes the rows of the y layers, then in the
+// remaining rows the columns of the x layers (every shell node once).  32-bit
+// index arithmetic: the host keeps the shell below 2^31 nodes.
+struct Shell {
+  unsigned nx, ny, nz, E, cz, cy, cx, mz, my, n0, n1, n2;
+  __host__ __device__ Shell(int e, int x, int y, int z) {
+    nx = x;
+    ny = y;
+    nz = z;
+    E = e;
+    cz = nz < 2u * E ? nz : 2u * E;
+    cy = ny < 2u * E ? ny : 2u * E;
+    cx = nx < 2u * E ? nx : 2u * E;
+    mz = nz - cz;
+    my = ny - cy;
+    n0 = cz * ny * nx;
+    n1 = mz * cy * nx;
+    n2 = mz * my * cx;
   }
-  t -= n1;
-  const int mz = nz - cz;
-  const long long n2 = static_cast<long long>(mz) * cy * nx;
-  if (t < n2) {
-    const long long row = static_cast<long long>(cy) * nx;
-    z = E + static_cast<int>(t / row);
-    const long long r = t % row;
-    const int k = static_cast<int>(r / nx);
-    y = k < E ? k : ny - cy + k;
-    x = static_cast<int>(r % nx);
-    return true;
+  __host__ __device__ unsigned count() const { return n0 + n1 + n2; }
+  __device__ void node(unsigned t, int &x, int &y, int &z) const {
+    if (t < n0) {
+      const unsigned k = t / (ny * nx), r = t - k * (ny * nx);
+      z = static_cast<int>(k < E ? k : nz - cz + k);
+      y = static_cast<int>(r / nx);
+      x = static_cast<int>(r - (r / nx) * nx);
+      return;
+    }
+    t -= n0;
+    if (t < n1) {
+      const unsigned row = t / nx, k = row % cy;
+      z = static_cast<int>(E + row / cy);
+      y = static_cast<int>(k < E ? k : ny - cy + k);
+      x = static_cast<int>(t - row * nx);
+      return;
+    }
+    t -= n1;
+    const unsigned row = t / cx, k = t - row * cx;
+    z = static_cast<int>(E + row / my);
+    y = static_cast<int>(E + row % my);
+    x = static_cast<int>(k < E ? k : nx - cx + k);
   }
-  t -= n2;
-  const int my = ny - cy;
-  const long long n3 = static_cast<long long>(mz) * my * cx;
-  if (t < n3) {
-    const long long per = static_cast<long long>(my) * cx;
-    z = E + static_cast<int>(t / per);
-    const long long r = t % per;
-    y = E + static_cast<int>(r / cx);
-    const int k = static_cast<int>(r % cx);
-    x = k < E ? k : nx - cx + k;
-    return true;
-  }
-  return false;
-}
-
-__host__ __device__ __forceinline__ long long shell_count(int E, int nx, int ny, int nz) {
-  const int cz = nz < 2 * E ? nz : 2 * E, cy = ny < 2 * E ? ny : 2 * E, cx = nx < 2 * E ? nx : 2 * E;
-  return static_cast<long long>(cz) * ny * nx + static_cast<long long>(nz - cz) * cy * nx +
-         static_cast<long long>(nz - cz) * (ny - cy) * cx;
-}
+};
 
 // Slab index along an axis of n nodes with layers of W nodes, or -1.
 __device__ __forceinline__ int slab_index(int i, int n, int W) {
@@ -922,84 +921,90 @@ __device__ __forceinline__ int slab_index(int i, int n, int W) {
   return -1;
 }
 
-// Offset of (x, y, z) with slab index s along axis a in that axis' slab array.
-__device__ __forceinline__ size_t slab_off(int a, int s, int x, int y, int z, const CpmlArgs &c) {
-  const size_t W2 = static_cast<size_t>(2 * c.W);
-  if (a == 0) return (static_cast<size_t>(z) * c.ny + y) * W2 + s;
-  if (a == 1) return (static_cast<size_t>(z) * W2 + s) * c.nx + x;
-  return (static_cast<size_t>(s) * c.ny + y) * c.nx + x;
+// Per-axis addressing of one node: coordinate i along the axis, axis length
+// n, field stride, and the node's offset in the axis' slab array without its
+// slab index (plus the slab stride), 32-bit.
+struct AxisAt {
+  int i, n;
+  unsigned stride, slab_rest, slab_stride;
+};
+
+__device__ __forceinline__ AxisAt axis_at(const CpmlArgs &c, int a, int x, int y, int z) {
+  const unsigned nx = c.nx, ny = c.ny, W2 = 2u * c.W;
+  AxisAt r;
+  if (a == 0) {
+    r = {x, c.nx, 1u, (static_cast<unsigned>(z) * ny + y) * W2, 1u};
+  } else if (a == 1) {
+    r = {y, c.ny, nx, static_cast<unsigned>(z) * W2 * nx + x, nx};
+  } else {
+    r = {z, c.nz, nx * ny, static_cast<unsigned>(y) * nx + x, ny * nx};
+  }
+  return r;
 }
 
-// Value of a [nz][ny][nx] field at (x, y, z) shifted by k along axis a; zero
-// outside the grid.
-__device__ __forceinline__ float field_at(const float *f, int a, int k, int x, int y, int z, int nx, int ny, int nz) {
-  int xx = x, yy = y, zz = z;
-  if (a == 0) xx += k;
-  else if (a == 1) yy += k;
-  else zz += k;
-  if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) return 0.f;
-  return f[(static_cast<size_t>(zz) * ny + yy) * nx + xx];
+// psi_a at the node k steps along the axis (zero outside the layers).
+__device__ __forceinline__ float psi_k(const CpmlArgs &c, int a, const AxisAt &A, int k) {
+  const int s = slab_index(A.i + k, A.n, c.W);
+  return s < 0 ? 0.f : c.psi[a][A.slab_rest + static_cast<unsigned>(s) * A.slab_stride];
 }
 
-__device__ __forceinline__ float psi_at(const CpmlArgs &c, int a, int k, int x, int y, int z) {
-  const int n = a == 0 ? c.nx : (a == 1 ? c.ny : c.nz);
-  const int i = (a == 0 ? x : (a == 1 ? y : z)) + k;
-  const int s = slab_index(i, n, c.W);
-  if (s < 0) return 0.f;
-  return c.psi[a][slab_off(a, s, a == 0 ? i : x, a == 1 ? i : y, a == 2 ? i : z, c)];
+// cur at the node k steps along the axis (zero outside the grid).
+__device__ __forceinline__ float cur_k(const float *cur, unsigned o, const AxisAt &A, int k) {
+  const int j = A.i + k;
+  return (j < 0 || j >= A.n) ? 0.f : cur[static_cast<int>(o) + k * static_cast<int>(A.stride)];
 }
 
-__global__ void cpml_psi_kernel(CpmlArgs c, const float *__restrict__ cur, long long count) {
-  const long long t = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
+// One thread per node of the W-node layers.
+__global__ void __launch_bounds__(256) cpml_psi_kernel(CpmlArgs c, const float *__restrict__ cur) {
+  const Shell S(c.W, c.nx, c.ny, c.nz);
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= S.count()) return;
   int x, y, z;
-  if (t >= count || !shell_node(t, c.W, c.nx, c.ny, c.nz, x, y, z)) return;
+  S.node(t, x, y, z);
+  const unsigned o = (static_cast<unsigned>(z) * c.ny + y) * c.nx + x;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int i = a == 0 ? x : (a == 1 ? y : z);
-    const int n = a == 0 ? c.nx : (a == 1 ? c.ny : c.nz);
-    const int s = slab_index(i, n, c.W);
+    const AxisAt A = axis_at(c, a, x, y, z);
+    const int s = slab_index(A.i, A.n, c.W);
     if (s < 0) continue;
     float d = 0.f;
 #pragma unroll
-    for (int m = 1; m <= R; ++m)
-      d = fmaf(c.d1w[a][m - 1],
-               field_at(cur, a, m, x, y, z, c.nx, c.ny, c.nz) - field_at(cur, a, -m, x, y, z, c.nx, c.ny, c.nz), d);
-    float *ps = c.psi[a] + slab_off(a, s, x, y, z, c);
-    *ps = fmaf(c.cb[a][i], *ps, c.ca[a][i] * d);
+    for (int m = 1; m <= R; ++m) d = fmaf(c.d1w[a][m - 1], cur_k(cur, o, A, m) - cur_k(cur, o, A, -m), d);
+    float *ps = c.psi[a] + A.slab_rest + static_cast<unsigned>(s) * A.slab_stride;
+    *ps = fmaf(c.cb[a][A.i], *ps, c.ca[a][A.i] * d);
   }
 }
 
-__global__ void cpml_fix_kernel(CpmlArgs c, const float *__restrict__ cur, const float *__restrict__ m,
-                                float *out, long long count) {
-  const long long t = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
+// One thread per node within W + R of a face.
+__global__ void __launch_bounds__(256) cpml_fix_kernel(CpmlArgs c, const float *__restrict__ cur,
+                                                       const float *__restrict__ m, float *out) {
+  const Shell S(c.W + R, c.nx, c.ny, c.nz);
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= S.count()) return;
   int x, y, z;
-  if (t >= count || !shell_node(t, c.W + R, c.nx, c.ny, c.nz, x, y, z)) return;
+  S.node(t, x, y, z);
+  const unsigned o = (static_cast<unsigned>(z) * c.ny + y) * c.nx + x;
   float extra = 0.f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int i = a == 0 ? x : (a == 1 ? y : z);
-    const int n = a == 0 ? c.nx : (a == 1 ? c.ny : c.nz);
-    if (i >= c.W + R && i < n - c.W - R) continue;  // psi_a and zeta_a vanish this far in
+    const AxisAt A = axis_at(c, a, x, y, z);
+    if (A.i >= c.W + R && A.i < A.n - c.W - R) continue;  // psi_a and zeta_a vanish this far in
     float dpsi = 0.f;
 #pragma unroll
-    for (int k = 1; k <= R; ++k)
-      dpsi = fmaf(c.d1w[a][k - 1], psi_at(c, a, k, x, y, z) - psi_at(c, a, -k, x, y, z), dpsi);
-    const int s = slab_index(i, n, c.W);
+    for (int k = 1; k <= R; ++k) dpsi = fmaf(c.d1w[a][k - 1], psi_k(c, a, A, k) - psi_k(c, a, A, -k), dpsi);
+    const int s = slab_index(A.i, A.n, c.W);
     if (s < 0) {
       extra += dpsi;
       continue;
     }
-    float d2 = c.d2w[a][0] * field_at(cur, a, 0, x, y, z, c.nx, c.ny, c.nz);
+    float d2 = c.d2w[a][0] * cur[o];
 #pragma unroll
-    for (int k = 1; k <= R; ++k)
-      d2 = fmaf(c.d2w[a][k],
-                field_at(cur, a, k, x, y, z, c.nx, c.ny, c.nz) + field_at(cur, a, -k, x, y, z, c.nx, c.ny, c.nz), d2);
-    float *ze = c.zeta[a] + slab_off(a, s, x, y, z, c);
-    const float zn = fmaf(c.cb[a][i], *ze, c.ca[a][i] * (d2 + dpsi));
+    for (int k = 1; k <= R; ++k) d2 = fmaf(c.d2w[a][k], cur_k(cur, o, A, k) + cur_k(cur, o, A, -k), d2);
+    float *ze = c.zeta[a] + A.slab_rest + static_cast<unsigned>(s) * A.slab_stride;
+    const float zn = fmaf(c.cb[a][A.i], *ze, c.ca[a][A.i] * (d2 + dpsi));
     *ze = zn;
     extra += dpsi + zn;
   }
-  const size_t o = (static_cast<size_t>(z) * c.ny + y) * c.nx + x;
   out[o] = fmaf(m[o], extra, out[o]);
 }
 
@@ -1349,17 +1354,16 @@ hipError_t launch_grad_final(const float *img, const float *m, float dt, float *
 }
 
 hipError_t launch_cpml_psi(const CpmlArgs &c, const float *cur, hipStream_t s) {
-  const long long n = shell_count(c.W, c.nx, c.ny, c.nz);
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(cpml_psi_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, c, cur, n);
+  const unsigned n = Shell(c.W, c.nx, c.ny, c.nz).count();
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(cpml_psi_kernel, dim3((n + 255) / 256), dim3(256), 0, s, c, cur);
   return hipGetLastError();
 }
 
 hipError_t launch_cpml_fix(const CpmlArgs &c, const float *cur, const float *m, float *out, hipStream_t s) {
-  const long long n = shell_count(c.W + kRadius, c.nx, c.ny, c.nz);
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(cpml_fix_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, c, cur, m, out,
-                     n);
+  const unsigned n = Shell(c.W + kRadius, c.nx, c.ny, c.nz).count();
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(cpml_fix_kernel, dim3((n + 255) / 256), dim3(256), 0, s, c, cur, m, out);
   return hipGetLastError();
 }
 

@@ -49,6 +49,12 @@ int validate(const wave_params *p) {
     if (2 * W > p->nx || 2 * W > p->ny || 2 * W > p->nz) return WAVE_EINVAL;
     if (!(p->cpml_reflection > 0.0 && p->cpml_reflection <= 1.0)) return WAVE_EINVAL;
     if (!std::isfinite(p->cpml_f0) || p->cpml_f0 < 0.0) return WAVE_EINVAL;
+    // the boundary shell (nodes within W + R of a face) is indexed with 32 bits
+    const int64_t E2 = 2 * (static_cast<int64_t>(W) + 4), nx = p->nx, ny = p->ny, nz = p->nz;
+    const int64_t mz = std::max<int64_t>(nz - E2, 0), my = std::max<int64_t>(ny - E2, 0);
+    const int64_t shell = std::min(E2, nz) * ny * nx + mz * std::min(E2, ny) * nx + mz * my * std::min(E2, nx);
+    if (shell >= (int64_t(1) << 31)) return WAVE_EINVAL;
+    if (nx * ny * nz >= (int64_t(1) << 31)) return WAVE_EINVAL;  // 32-bit node offsets in the CPML kernels
   }
   if (p->storage < WAVE_F32 || p->storage > WAVE_BF16) return WAVE_EINVAL;
   if (p->src[0] >= 0) {

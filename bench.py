@@ -212,7 +212,7 @@ def kernel_study_leg(nt: int = 20) -> dict:
     wav = torch.from_numpy(W.wavelet(max(nt, 50))).to(dev)
     traces = torch.empty((max(nt, 50), len(W.rec)), dtype=torch.float32, device=dev)
     kernels = {"gmem (3D blocks 64x4x4, global memory)": 14, "smem (3D blocks 64x4x4 + halo in LDS)": 15,
-               "2.5D 64x32, 1 node/lane, 3 planes in flight": 0, "2.5D 64x32, 1 node/lane, 1 plane in flight": 5,
+               "2.5D 64x32, 1 node/lane, 3 planes in flight": 18, "2.5D 64x32, 1 node/lane, 1 plane in flight": 5,
                "2.5D 256x8, 4 nodes/lane": 12, "2.5D 128x32, 2 nodes/lane (automatic at 1024^2 planes)": 11,
                "2.5D semi-stencil 64x32, 1 node/lane": 16, "2.5D semi-stencil 256x8, 4 nodes/lane": 17}
     out = {"workload": f"{W.name}, float32, Dirichlet, {nt} timed steps per kernel",

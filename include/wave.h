@@ -168,6 +168,21 @@ int wave_read_field(wave_t w, int32_t which, float *out_dev);
 /* Host copy of the step counter n (steps since the last reset). */
 int wave_time_index(wave_t w, int32_t *n);
 
+/* Shot snapshots: the complete state of a forward run after its last
+ * enqueued step (step counter, both stored time levels -- A^n and A^{n-1}, or
+ * A^n and V^n with 16-bit storage -- their scale records, and the CPML memory
+ * variables), so that the per-iteration update of paper Sec. II continues
+ * from it bit for bit.  wave_state_bytes gives the size; wave_save_state
+ * copies the state to `dst_dev` (caller-owned device memory of at least that
+ * size) and wave_load_state restores it into a context created with the same
+ * grid, storage and boundary parameters (the same or another context, e.g. to
+ * resume a preempted shot).  Both synchronise the context's stream.  Errors:
+ * WAVE_EINVAL (null arguments; a snapshot from a context with other
+ * parameters), WAVE_EHIP. */
+int wave_state_bytes(wave_t w, size_t *bytes);
+int wave_save_state(wave_t w, void *dst_dev);
+int wave_load_state(wave_t w, const void *src_dev);
+
 /* Synchronise the stream and report WAVE_FLAG_* bits for the current field
  * (WAVE_FLAG_NONFINITE: A^n holds an infinity or NaN). */
 int wave_sync_status(wave_t w, uint32_t *flags);
@@ -182,6 +197,8 @@ int wave_variant_count(void);
  * info[0..4] (caller-owned host array of 5): family, by, ry, pd, vec.
  * Family 0 is the 2.5D blocking of paper Sec. IV-A (tile x and y, stream
  * along z): tiles of 64*vec x by*ry nodes, pd planes of loads in flight.
+ * Variant 0 means "automatic"; its info is the shape that choice falls back
+ * to (also available explicitly as another variant).
  * Families 1 and 2 are the paper's 3D-blocking designs of the same section
  * ("gmem": every stencil value from global memory; "smem": a 3D tile with
  * its halo staged in shared memory): blocks of 64 x by x ry nodes, float32

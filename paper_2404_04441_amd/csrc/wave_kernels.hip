@@ -1152,8 +1152,9 @@ unsigned grid_for(size_t n, unsigned block) {
 }
 
 // Kernel variants (FAMILY, BY, RY, PD, VEC).  Family 0 is the 2.5D streaming
-// step_kernel (tile 64*VEC x BY*RY, PD planes in flight); variant 0 is also
-// the shape the runtime's automatic choice falls back to.  Families 1 (gmem)
+// step_kernel (tile 64*VEC x BY*RY, PD planes in flight).  Variant 0 asks the
+// runtime for its automatic choice; its row is the shape that choice falls
+// back to, which variant 18 requests explicitly.  Families 1 (gmem)
 // and 2 (smem) are the 3D-blocked kernels with blocks of 64 x BY x RY nodes;
 // family 3 is the 2.5D kernel with the semi-stencil z sum.
 #define WAVE_VARIANTS(X)  \
@@ -1174,7 +1175,8 @@ unsigned grid_for(size_t n, unsigned block) {
   X(14, 1, 4, 4, 1, 1)    \
   X(15, 2, 4, 4, 1, 1)    \
   X(16, 3, 8, 4, 3, 1)    \
-  X(17, 3, 8, 1, 3, 4)
+  X(17, 3, 8, 1, 3, 4)    \
+  X(18, 0, 8, 4, 3, 1)
 
 #define WAVE_VARIANT_INFO(id, fam, by, ry, pd, vec) {by, ry, pd, vec, fam},
 constexpr Variant kVariants[] = {WAVE_VARIANTS(WAVE_VARIANT_INFO)};

@@ -771,6 +771,94 @@ int wave_read_field(wave_t w, int32_t which, float *out_dev) {
                                    w->p.ny, w->p.nz, w->st, w->stream));
 }
 
+// Snapshot layout: 256-B header | step state | A fields 0 and 1 | V (16-bit)
+// | CPML slabs, each section 256-B aligned; interiors only (the padding
+// planes are zero in every context).
+namespace {
+struct StateHeader {
+  uint64_t magic, bytes, field_bytes, slab_bytes;
+  int32_t n, nx, ny, nz, storage, cpml_width, pad[2];
+};
+constexpr uint64_t kStateMagic = 0x31544154534556ull;  // "VESTAT1"
+
+size_t state_bytes(const wave_ctx *w, size_t *field_bytes, size_t *slabs) {
+  const size_t es = w->p.storage == WAVE_F32 ? 4 : 2;
+  *field_bytes = es * w->N;
+  *slabs = 0;
+  if (w->cpml)
+    for (int a = 0; a < 3; ++a) *slabs += slab_bytes(w, a);
+  const int nfields = w->p.storage == WAVE_F32 ? 2 : 3;
+  return 256 + 256 + nfields * align256(*field_bytes) + align256(*slabs);
+}
+}  // namespace
+
+int wave_state_bytes(wave_t w, size_t *bytes) {
+  if (!w || !bytes) return WAVE_EINVAL;
+  size_t fb, sb;
+  *bytes = state_bytes(w, &fb, &sb);
+  return WAVE_OK;
+}
+
+int wave_save_state(wave_t w, void *dst_dev) {
+  if (!w || !dst_dev) return WAVE_EINVAL;
+  size_t fb, sb;
+  const size_t total = state_bytes(w, &fb, &sb);
+  StateHeader h{};
+  h.magic = kStateMagic;
+  h.bytes = total;
+  h.field_bytes = fb;
+  h.slab_bytes = sb;
+  h.n = w->n;
+  h.nx = w->p.nx;
+  h.ny = w->p.ny;
+  h.nz = w->p.nz;
+  h.storage = w->p.storage;
+  h.cpml_width = w->p.cpml_width;
+  char *d = static_cast<char *>(dst_dev);
+  int rc = hip_rc(hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, w->stream));
+  if (!rc) rc = hip_rc(hipMemcpyAsync(d + 256, w->st, sizeof(StepState), hipMemcpyDeviceToDevice, w->stream));
+  size_t off = 512;
+  void *fields[3] = {w->fa, w->fb, w->fv};
+  const int nfields = w->p.storage == WAVE_F32 ? 2 : 3;
+  for (int k = 0; k < nfields && !rc; ++k, off += align256(fb))
+    rc = hip_rc(hipMemcpyAsync(d + off, fields[k], fb, hipMemcpyDeviceToDevice, w->stream));
+  for (int a = 0; a < 3 && w->cpml && !rc; ++a) {
+    rc = hip_rc(hipMemcpyAsync(d + off, w->ws + w->L.cpml_slab[a], slab_bytes(w, a), hipMemcpyDeviceToDevice,
+                               w->stream));
+    off += slab_bytes(w, a);
+  }
+  if (!rc) rc = hip_rc(hipStreamSynchronize(w->stream));  // the header's host copy stays valid until here
+  return rc;
+}
+
+int wave_load_state(wave_t w, const void *src_dev) {
+  if (!w || !src_dev) return WAVE_EINVAL;
+  size_t fb, sb;
+  const size_t total = state_bytes(w, &fb, &sb);
+  StateHeader h{};
+  const char *src = static_cast<const char *>(src_dev);
+  int rc = hip_rc(hipMemcpyAsync(&h, src, sizeof(h), hipMemcpyDeviceToHost, w->stream));
+  if (!rc) rc = hip_rc(hipStreamSynchronize(w->stream));
+  if (rc) return rc;
+  if (h.magic != kStateMagic || h.bytes != total || h.field_bytes != fb || h.slab_bytes != sb || h.nx != w->p.nx ||
+      h.ny != w->p.ny || h.nz != w->p.nz || h.storage != w->p.storage || h.cpml_width != w->p.cpml_width || h.n < 0)
+    return WAVE_EINVAL;
+  rc = hip_rc(hipMemcpyAsync(w->st, src + 256, sizeof(StepState), hipMemcpyDeviceToDevice, w->stream));
+  size_t off = 512;
+  void *fields[3] = {w->fa, w->fb, w->fv};
+  const int nfields = w->p.storage == WAVE_F32 ? 2 : 3;
+  for (int k = 0; k < nfields && !rc; ++k, off += align256(fb))
+    rc = hip_rc(hipMemcpyAsync(fields[k], src + off, fb, hipMemcpyDeviceToDevice, w->stream));
+  for (int a = 0; a < 3 && w->cpml && !rc; ++a) {
+    rc = hip_rc(hipMemcpyAsync(w->ws + w->L.cpml_slab[a], src + off, slab_bytes(w, a), hipMemcpyDeviceToDevice,
+                               w->stream));
+    off += slab_bytes(w, a);
+  }
+  if (!rc) rc = hip_rc(hipStreamSynchronize(w->stream));
+  if (!rc) w->n = h.n;
+  return rc;
+}
+
 int wave_time_index(wave_t w, int32_t *n) {
   if (!w || !n) return WAVE_EINVAL;
   *n = w->n;

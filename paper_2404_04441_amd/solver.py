@@ -160,6 +160,21 @@ class Solver:
         L.check(L.lib().wave_read_field(self._h, int(which), _ptr(out)), "wave_read_field")
         return out
 
+    def save_state(self, out=None) -> torch.Tensor:
+        """Snapshot of the shot (device bytes) that ``load_state`` resumes from."""
+        n = ctypes.c_size_t()
+        L.check(L.lib().wave_state_bytes(self._h, ctypes.byref(n)), "wave_state_bytes")
+        if out is None:
+            out = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        if out.numel() * out.element_size() < n.value or not out.is_cuda:
+            raise ValueError(f"snapshot buffer must be a device tensor of at least {n.value} bytes")
+        L.check(L.lib().wave_save_state(self._h, ctypes.c_void_p(out.data_ptr())), "wave_save_state")
+        return out
+
+    def load_state(self, snapshot: torch.Tensor):
+        """Resume from a snapshot taken from a solver with the same parameters."""
+        L.check(L.lib().wave_load_state(self._h, ctypes.c_void_p(snapshot.data_ptr())), "wave_load_state")
+
     def time_index(self) -> int:
         n = ctypes.c_int32()
         L.check(L.lib().wave_time_index(self._h, ctypes.byref(n)), "wave_time_index")

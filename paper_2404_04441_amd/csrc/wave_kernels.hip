@@ -5,22 +5,32 @@
 // source and receivers in the same pass.  Blocking follows the 2.5D idea of
 // paper Sec. IV-A (tile x and y, stream along z) redesigned for CDNA4:
 //
-//  * a workgroup owns a 64 x TY column of the grid (TY = BY*RY rows) over a
-//    z-chunk; each 64-lane wavefront owns RY consecutive rows, so every global
-//    access of the interior is a fully coalesced 256-byte row whose address
-//    is wavefront-uniform (scalar row base + one shared lane offset);
+//  * a workgroup owns a (64*VEC) x (BY*RY) column of the grid over a z-chunk;
+//    each 64-lane wavefront owns RY consecutive rows and each lane VEC
+//    consecutive x nodes, so every global access of the interior is one
+//    coalesced row of 256*VEC bytes;
+//  * each field has one buffer resource per workgroup; the plane is the
+//    scalar offset, the row and column one lane register.  Lanes outside the
+//    grid use an offset past the resource's end (loads read zero, stores are
+//    dropped) and the fields carry zero padding planes past nz, so the z loop
+//    has no clamps, selects or store branches;
 //  * the centre xy plane (with its radius-4 x/y halo) is staged in LDS, double
-//    buffered so one barrier per plane suffices; y neighbours inside a
-//    wavefront's own rows come from registers instead;
-//  * the 9 values each thread needs along z live in a register queue that
-//    shifts by one plane per iteration; A^n is read from HBM once per chunk;
+//    buffered so one barrier per plane suffices; x neighbours are read as one
+//    aligned window per lane, y neighbours inside a wavefront's own rows come
+//    from registers;
+//  * the 9 values each thread needs along z live in a register queue with
+//    compile-time slots; A^n is read from HBM once per chunk;
 //  * loads run PD planes ahead of the plane being computed (a register
 //    pipeline), so enough bytes are in flight to cover HBM latency;
 //  * A^{n-1}, m and A^{n+1} are touched exactly once: they use nontemporal
 //    loads/stores so that L2 keeps the A^n planes the neighbours' halos need;
 //  * workgroup ids are remapped so that each XCD (hardware dispatches ids
 //    round-robin over the 8 XCDs) owns a contiguous run of tiles, keeping
-//    y-halo re-reads inside one XCD's L2.
+//    halo re-reads inside one XCD's L2.
+//
+// Beside it: the paper's 3D-blocked designs (gmem, smem) and a semi-stencil
+// form for the kernel study, the CPML boundary kernels, and small utility
+// kernels (setup, decode, gather/scatter, gradient, fills).
 #include <hip/hip_runtime.h>
 
 #include <utility>

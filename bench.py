@@ -139,22 +139,27 @@ def storage_forms_leg(W, vel_dev, nt: int) -> dict:
 
 def cpml_leg(W, vel_dev, nt: int) -> dict:
     """The 512^3 workload with CPML layers of 20 nodes (the paper's boundary)
-    instead of the sponge: time per step of the whole step (memory-variable
-    update, fused step, boundary correction, receiver gather), float32."""
+    instead of the sponge, float32: time per step of all kernels of a step.
+    "fused": the automatic shape, whose step kernel applies the boundary terms
+    (memory-variable pass + step).  "separate": variant 9 (same 4-node lanes,
+    no fused kernel): memory-variable pass, plain step, boundary correction
+    pass, receiver gather."""
     import torch
 
     from paper_2404_04441_amd import Solver
 
     wav = torch.from_numpy(W.wavelet(nt)).to(vel_dev.device)
     traces = torch.empty((nt, len(W.rec)), dtype=torch.float32, device=vel_dev.device)
-    s = Solver(vel_dev, W.h, W.dt, src=W.src, rec=W.rec, cpml_width=W.sponge_width, cpml_f0=W.f0)
-    s.run(10, wav, traces)
-    r = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT["f32"])
-    s.close()
-    r = {"step_ms": r["kernel_ms"], "gpts_per_s": r["gpts_per_s"],
-         "note": "all kernels of a step; roofline fraction at 16 B/pt for comparison", "roofline_frac": r["roofline_frac"],
-         "layers": W.sponge_width, "reflection": 1e-3, "f0_hz": W.f0}
-    return r
+    out = {"layers": W.sponge_width, "reflection": 1e-3, "f0_hz": W.f0,
+           "note": "all kernels of a step; roofline fraction at 16 B/pt for comparison"}
+    for name, variant in (("fused", 0), ("separate", 9)):
+        s = Solver(vel_dev, W.h, W.dt, src=W.src, rec=W.rec, cpml_width=W.sponge_width, cpml_f0=W.f0,
+                   variant=variant)
+        s.run(10, wav, traces)
+        r = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT["f32"])
+        s.close()
+        out[name] = {"step_ms": r["kernel_ms"], "gpts_per_s": r["gpts_per_s"], "roofline_frac": r["roofline_frac"]}
+    return out
 
 
 def precision_leg(nt: int = 500) -> dict:

@@ -91,12 +91,17 @@ typedef struct {
   int32_t tune;              /* 1 with variant = 0 and zchunk = 0: wave_create times the candidate
                                 2.5D shapes and z-chunks for a few steps on the fresh (zero) fields
                                 and keeps the fastest; the choice is cached per (nx, ny, nz,
-                                storage) for the life of the process.  Every choice computes the
-                                same bits.  0: the fixed automatic rule */
+                                storage, CPML or not) for the life of the process.  Every
+                                choice computes the same bits.  0: the fixed automatic rule */
   int32_t cpml_width;        /* >0: CPML absorbing layers of this many nodes on all six faces (the
                                 boundary of paper Sec. II / IV-A; float32, forward only, needs
-                                sponge_width = 0, 2*cpml_width <= nx, ny, nz and nx*ny*nz < 2^31);
-                                0: none */
+                                sponge_width = 0, 2*cpml_width <= nx, ny, nz, nx*ny*nz < 2^31 and
+                                each memory-variable array, 4 * 2*cpml_width * (largest of nx*ny,
+                                ny*nz, nx*nz) bytes, < 2^31).  2.5D shapes with at most 2 rows per
+                                wavefront and 4 nodes per lane (the automatic choice is one) apply
+                                the x part of the boundary terms inside the step kernel; other
+                                shapes apply all of it in a correction pass.  With tune = 1 only
+                                the former are timed.  0: none */
   double cpml_reflection;    /* CPML target reflection coefficient R in (0, 1] (default 1e-3):
                                 d(xi) = -3 v_max ln(R) xi^2 / (2 W h) */
   double cpml_f0;            /* CPML frequency shift alpha(xi) = pi f0 (1 - xi), Hz (default 0) */

@@ -35,6 +35,7 @@ struct Coef {
   float kx[4];     // c_m / dx^2
   float ky[4];
   float kz[4];
+  float k0a[3];    // c0 / h_a^2 per axis (the CPML form needs the per-axis second derivatives)
 };
 
 // Receivers forming a regular box, listed x fastest then y then z:
@@ -47,6 +48,20 @@ struct RecBox {
 };
 
 enum Storage { kF32 = 0, kF16 = 1, kBF16 = 2 };
+
+// CPML boundary (float32 forward): memory variables psi_a, zeta_a in slab
+// arrays over the W-node layers of each axis -- x: [nz][ny][2W], y:
+// [nz][2W][nx], z: [2W][ny][nx]; slab index s = i for i < W and
+// i - (n - 2W) for i >= n - W.
+struct CpmlArgs {
+  float *psi[3], *zeta[3];   // x, y, z
+  const float *ca[3];        // a coefficient per node along each axis (n_a entries)
+  const float *cb[3];        // b coefficient
+  float d1w[3][4];           // w_m / h_a (first derivative)
+  float d2w[3][5];           // c_m / h_a^2 (second derivative, c_0 first)
+  int W;                     // layer width in nodes (2W <= every axis)
+  int nx, ny, nz;
+};
 
 // Float32 storage keeps (A^n, A^{n-1}) and writes A^{n+1} over A^{n-1}.
 // 16-bit storage keeps (A^n, V^n = A^n - g A^{n-1}): `prev` and `vout` both
@@ -76,20 +91,11 @@ struct StepArgs {
   float *img;         // accumulator sum_k mu^{k+1} L(A^k)
   const float *resid; // [nt][nrec] residual, injected at receivers
   int resid_row;      // row of resid injected by this launch
-};
-
-// CPML boundary (float32 forward): memory variables psi_a, zeta_a in slab
-// arrays over the W-node layers of each axis -- x: [nz][ny][2W], y:
-// [nz][2W][nx], z: [2W][ny][nx]; slab index s = i for i < W and
-// i - (n - 2W) for i >= n - W.
-struct CpmlArgs {
-  float *psi[3], *zeta[3];   // x, y, z
-  const float *ca[3];        // a coefficient per node along each axis (n_a entries)
-  const float *cb[3];        // b coefficient
-  float d1w[3][4];           // w_m / h_a (first derivative)
-  float d2w[3][5];           // c_m / h_a^2 (second derivative, c_0 first)
-  int W;                     // layer width in nodes (2W <= every axis)
-  int nx, ny, nz;
+  // CPML (float32 forward, 2.5D kernels): 1 = add the x part of the boundary
+  // terms and update zeta_x inside the step (psi is updated by a pass before
+  // it, the y and z parts by a pass after it)
+  int cpml;
+  CpmlArgs cp;
 };
 
 struct Variant {
@@ -104,8 +110,11 @@ struct Variant {
 
 int variant_count();
 Variant variant_info(int v);
-// Workgroups of the forward step kernel that fit on one CU at once.
-int step_blocks_per_cu(int storage, int variant);
+// True for the float32 2.5D shapes whose step kernel has the CPML boundary fused in.
+bool variant_fuses_cpml(int v);
+// Workgroups of the forward step kernel that fit on one CU at once (cpml: the
+// fused CPML kernel where the shape has one).
+int step_blocks_per_cu(int storage, int variant, bool cpml);
 
 // Launchers; each returns the hipError_t of the launch.
 hipError_t launch_step(int storage, int variant, bool adjoint, const StepArgs &a, hipStream_t s);
@@ -129,7 +138,9 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 // psi_a^n = b psi_a^{n-1} + a D1_a cur, on the W-node layers
 hipError_t launch_cpml_psi(const CpmlArgs &c, const float *cur, hipStream_t s);
 // out += m * sum_a (D1_a psi_a + zeta_a), zeta_a = b zeta_a + a (D2_a cur + D1_a psi_a),
-// on the nodes within W + R of a face
-hipError_t launch_cpml_fix(const CpmlArgs &c, const float *cur, const float *m, float *out, hipStream_t s);
+// on the nodes within W + R of a face; yz_only: axes y and z only, on the
+// z-layer planes and y-layer rows of that shell (the x part is fused in the step)
+hipError_t launch_cpml_fix(const CpmlArgs &c, const float *cur, const float *m, float *out, bool yz_only,
+                           hipStream_t s);
 
 }  // namespace wave

@@ -210,12 +210,20 @@ template <int VEC> __device__ __forceinline__ void lds_get(const float *p, float
   }
 }
 
+// Slab index along an axis of n nodes with layers of W nodes, or -1.
+__device__ __forceinline__ int slab_index(int i, int n, int W) {
+  if (i < 0 || i >= n) return -1;
+  if (i < W) return i;
+  if (i >= n - W) return i - (n - 2 * W);
+  return -1;
+}
+
 // Registers one thread holds for one z-plane of the pipeline: raw loaded
 // rows, so that nothing waits on a load until the plane is consumed.  Every
 // vector-memory load of the z loop lives here: s_waitcnt vmcnt retires loads
 // in issue order, so a load consumed in the same iteration would also wait for
 // every prefetch issued before it.
-template <int S, int RY, int VEC, int NYH, bool ADJ>
+template <int S, int RY, int VEC, int NYH, bool ADJ, bool CP>
 struct Stage {
   static constexpr int NA = VEC * (S == kF32 ? 4 : 2);  // bytes of one A-type row
   static constexpr int NF = VEC * 4;                    // bytes of one float row
@@ -231,6 +239,9 @@ struct Stage {
   Words<NF> yhF[ADJ ? NYH : 1];
   float xhF;
   float res[ADJ ? RY : 1][ADJ ? VEC : 1];  // adjoint: residual injected at receivers of plane z
+  float psx[CP ? RY : 1][CP ? VEC : 1];  // CPML: psi_x at the lane's columns (0 off the x layers)
+  float zex[CP ? RY : 1][CP ? VEC : 1];  // CPML: zeta_x at the lane's columns
+  float psxh;                            // CPML: psi_x at this lane's x-halo node (lanes < 8*RY)
 };
 
 constexpr int kQ = 2 * R + 1;  // z-queue length (planes z-4 .. z+4)
@@ -250,10 +261,19 @@ static_assert(kPadZ >= (kQ - 1) + kMaxPD + R, "z padding must cover the last tri
 // Sec. IV-A): the left half sum_m kz_m A(z-m) of plane z is summed R planes
 // early, at the position of plane z-R (from planes z-R .. z-1), so only planes
 // z .. z+R stay live in the queue; the right half is added when z is computed.
-template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ>
+// CP: the x part of the CPML boundary fused into the step (float32 forward;
+// psi_a^n is already updated by cpml_psi_kernel).  The Laplacian is summed
+// per axis, and every node adds D1_x psi_x^n + zeta_x^n, with zeta_x updated
+// in place on the x layers.  Off the layers psi_x and zeta_x read as zero,
+// so this needs no branch.  psi_x and zeta_x come through the prefetch
+// pipeline; psi_x is staged in LDS like A^n (its x neighbours are other
+// lanes' values).  The y and z parts follow in cpml_fix_kernel over the rows
+// and planes within W + R of a y or z face: in the streaming kernel their
+// neighbours would be loads the z loop waits on in every such row and plane.
+template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ, bool CP>
 __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   using C = Codec<S>;
-  using StageT = Stage<S, RY, VEC, (2 * R + BY - 1) / BY, ADJ>;
+  using StageT = Stage<S, RY, VEC, (2 * R + BY - 1) / BY, ADJ, CP>;
   constexpr int NA = StageT::NA, NF = StageT::NF;
   constexpr int TX = kTileX * VEC;
   constexpr int TY = BY * RY;
@@ -266,12 +286,17 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   static_assert(PD <= kMaxPD, "z padding assumes at most kMaxPD planes in flight");
   static_assert(VEC == 1 || VEC == 2 || VEC == 4, "lane width");
   static_assert(!(SEMI && ADJ), "the semi-stencil form is forward only");
+  static_assert(!CP || (S == kF32 && !SEMI && !ADJ), "the fused CPML step is float32 forward");
   // each LDS plane ends with a scratch row: halo writes of lanes or
   // wavefronts with nothing to write go there, so no write is predicated
   constexpr int LP = LH * LW + 64 * VEC;
   constexpr int DUMMY = LH * LW;
   __shared__ __attribute__((aligned(16))) float lds[2][LP];
   __shared__ __attribute__((aligned(16))) float ldsF[ADJ ? 2 : 1][ADJ ? LP : 1];
+  // CPML: psi_x rows of the tile (TY rows of LW, no y halo) and a scratch row
+  constexpr int LPX = TY * LW + 64 * VEC;
+  constexpr int DUMMYX = TY * LW;
+  __shared__ __attribute__((aligned(16))) float ldsX[CP ? 2 : 1][CP ? LPX : 1];
   __shared__ float red[BY], redv[BY];
 
   // XCD-aware tile order: hardware id b runs on XCD b % 8.
@@ -399,19 +424,50 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
     vyh_f[i] = ok ? e * 4u : kOOB;
   }
   // x-halo: lane l < 8*RY covers row l/8 of this wavefront, column l%8
-  int xhlds = DUMMY + lane;
+  int xhlds = DUMMY + lane, xhx = DUMMYX + lane, xh_x = -1, xh_y = 0;
   uint32_t vxh = kOOB, vxh_f = kOOB;
   if (lane < 8 * RY) {
     const int j = lane >> 3, c = lane & 7;
     const int gxx = c < R ? x0 - R + c : x0 + TX + (c - R);
     const int yj = yb + j;
     xhlds = (R + w * RY + j) * LW + (c < R ? c : TX + c);
+    xhx = (w * RY + j) * LW + (c < R ? c : TX + c);
+    if (yj < ny) {
+      xh_x = gxx;
+      xh_y = yj;
+    }
     if (gxx >= 0 && gxx < nx && yj < ny) {
       const uint32_t e = static_cast<uint32_t>(yj) * static_cast<uint32_t>(nx) + static_cast<uint32_t>(gxx);
       vxh = e * ES;
       vxh_f = e * 4u;
     }
   }
+
+  // ---- CPML (fused x part): one resource per x slab array (the host keeps
+  // it below 2^31 bytes; loads outside it read zero), the x profile at this
+  // lane's columns, and whether any of those columns lies in an x layer
+  const int W = CP ? a.cp.W : 0;
+  const uint32_t W2 = 2u * static_cast<uint32_t>(W);
+  const uint32_t uny = static_cast<uint32_t>(ny);
+  rsrc_t rPX = rnull, rZX = rnull;
+  float cax[CP ? VEC : 1], cbx[CP ? VEC : 1];
+  bool xown = false;  // some of this lane's columns lie in an x layer
+  if constexpr (CP) {
+    const uint32_t bx = static_cast<uint32_t>(a.nz) * uny * W2 * 4u;
+    rPX = make_rsrc(a.cp.psi[0], bx);
+    rZX = make_rsrc(a.cp.zeta[0], bx);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      cax[i] = xin ? a.cp.ca[0][x + i] : 0.f;
+      cbx[i] = xin ? a.cp.cb[0][x + i] : 0.f;
+    }
+    xown = xin && (x < W || x + VEC - 1 >= nx - W);
+  }
+  // byte offset of node (c, yj) in a plane of the x slabs, or kOOB off the x layers
+  auto xoff = [&](int c, int yj) {
+    const int sx = slab_index(c, nx, W);
+    return sx >= 0 ? (static_cast<uint32_t>(yj) * W2 + static_cast<uint32_t>(sx)) * 4u : kOOB;
+  };
 
   auto rec_plane = [&](int z) {  // receiver-box index of plane z, or -1
     int rzi = -1;
@@ -466,6 +522,22 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
           st.res[j][i] = __uint_as_float(ld_words<4, 0>(rres, ridx, 0u).w[0]);
         }
     }
+    if constexpr (CP) {  // x slab plane z (none past nz); zero off the x layers
+      const bool zin = z < a.nz;
+      const rsrc_t rp = zin ? rPX : rnull, rz = zin ? rZX : rnull;
+      const uint32_t sp = zin ? static_cast<uint32_t>(z) * uny * W2 * 4u : 0u;
+#pragma unroll
+      for (int j = 0; j < RY; ++j) {
+        const int yj = yb + j;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+          const uint32_t o = (xown && yj < ny) ? xoff(x + i, yj) : kOOB;
+          st.psx[j][i] = __uint_as_float(ld_words<4, 0>(rp, o, sp).w[0]);
+          st.zex[j][i] = __uint_as_float(ld_words<4, 0>(rz, o, sp).w[0]);
+        }
+      }
+      st.psxh = __uint_as_float(ld_words<4, 0>(rp, xh_x >= 0 ? xoff(xh_x, xh_y) : kOOB, sp).w[0]);
+    }
   };
 
   // ---- prologue: queue slot (p - zb + R) mod 9 holds plane p; stages hold planes zb .. zb+PD-1
@@ -516,8 +588,11 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   // neighbours from the queue Q, x neighbours from a window of the LDS row,
   // y neighbours from this lane's own rows when they lie in the strip, else
   // from the LDS rows above and below.
+  // CP: also the per-axis parts lax[a] (centre weight c_0 / h_a^2 each), and
+  // lap = (lax[0] + lax[1]) + lax[2].
   auto laplacian = [&](const float (&Q)[kQ][RY][VEC], const float *Lp, int cs, int s0, int j, float *lap,
-                       const float (&Xp)[SEMI ? kQ : 1][RY][VEC]) __attribute__((always_inline)) {
+                       const float (&Xp)[SEMI ? kQ : 1][RY][VEC], float (&lax)[3][VEC])
+                       __attribute__((always_inline)) {
     const float *row = Lp + (R + w * RY + j) * LW + VEC * lane;  // window start: column x - R
     float win[VEC + 2 * R];
 #pragma unroll
@@ -527,6 +602,10 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
     for (int i = 0; i < VEC; ++i) {
       if (VEC == 1) win[R] = Q[cs][j][0];
       lap[i] = a.c.k0 * Q[cs][j][i];
+      if constexpr (CP) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) lax[d][i] = a.c.k0a[d] * Q[cs][j][i];
+      }
     }
 #pragma unroll
     for (int m = 1; m <= R; ++m) {
@@ -545,11 +624,21 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       }
 #pragma unroll
       for (int i = 0; i < VEC; ++i) {
-        lap[i] = fmaf(a.c.kx[m - 1], win[R + i + m] + win[R + i - m], lap[i]);
-        lap[i] = fmaf(a.c.ky[m - 1], yp[i] + ym[i], lap[i]);
-        if constexpr (!SEMI)
-          lap[i] = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i] + Q[(s0 + R - m + kQ) % kQ][j][i], lap[i]);
+        if constexpr (CP) {
+          lax[0][i] = fmaf(a.c.kx[m - 1], win[R + i + m] + win[R + i - m], lax[0][i]);
+          lax[1][i] = fmaf(a.c.ky[m - 1], yp[i] + ym[i], lax[1][i]);
+          lax[2][i] = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i] + Q[(s0 + R - m + kQ) % kQ][j][i], lax[2][i]);
+        } else {
+          lap[i] = fmaf(a.c.kx[m - 1], win[R + i + m] + win[R + i - m], lap[i]);
+          lap[i] = fmaf(a.c.ky[m - 1], yp[i] + ym[i], lap[i]);
+          if constexpr (!SEMI)
+            lap[i] = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i] + Q[(s0 + R - m + kQ) % kQ][j][i], lap[i]);
+        }
       }
+    }
+    if constexpr (CP) {
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) lap[i] = (lax[0][i] + lax[1][i]) + lax[2][i];
     }
     if constexpr (SEMI) {  // left half from the partial, right half from the queue
 #pragma unroll
@@ -608,6 +697,17 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       }
       L[xhlds] = row_get<S>(cs.xh, 0) * inv_cur;
       if constexpr (ADJ) LF[xhlds] = cs.xhF;
+      float *LX = ldsX[CP ? par : 0];
+      float zex[CP ? RY : 1][CP ? VEC : 1];
+      if constexpr (CP) {
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+          lds_put<VEC>(LX + (w * RY + j) * LW + R + VEC * lane, cs.psx[j]);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) zex[j][i] = cs.zex[j][i];
+        }
+        LX[xhx] = cs.psxh;
+      }
       float pc[RY][VEC], mc[RY][VEC], ic[RY][VEC], rc[RY][VEC];
 #pragma unroll
       for (int j = 0; j < RY; ++j)
@@ -624,6 +724,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       __syncthreads();
 
       const uint32_t sz0 = so(z), sz0f = so_f(z);
+      const bool zin = z < a.nz;
       // source term of this plane, per column of the lane's VEC nodes
       float wsp[VEC];
 #pragma unroll
@@ -631,8 +732,36 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       float outv[RY][VEC];
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
-        float lap[VEC];
-        laplacian(q, L, cslot, s, j, lap, X);
+        float lap[VEC], lax[3][VEC];
+        laplacian(q, L, cslot, s, j, lap, X, lax);
+        if constexpr (CP) {  // x part of the CPML terms: D1_x psi_x + zeta_x, zeta_x updated
+          const int yj = yb + j;
+          float ext[VEC], zn[VEC];
+          // x: every lane, psi_x window (columns x-R .. x+VEC+R-1) from LDS;
+          // psi_x and zeta_x are zero off the layers
+          {
+            float px[VEC + 2 * R];
+            const float *xrow = LX + (w * RY + j) * LW + VEC * lane;
+#pragma unroll
+            for (int k = 0; k < (VEC + 2 * R) / VEC; ++k) lds_get<VEC>(xrow + VEC * k, px + VEC * k);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+              float d = 0.f;
+#pragma unroll
+              for (int k = 1; k <= R; ++k) d = fmaf(a.cp.d1w[0][k - 1], px[R + i + k] - px[R + i - k], d);
+              zn[i] = fmaf(cbx[i], zex[j][i], cax[i] * (lax[0][i] + d));
+              ext[i] = d + zn[i];
+            }
+          }
+          if (xown && zin && yj < ny) {
+            const uint32_t sp = static_cast<uint32_t>(z) * uny * W2 * 4u;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i)
+              st_words<4, 0>(Words<4>{{__float_as_uint(zn[i])}}, rZX, xoff(x + i, yj), sp);
+          }
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) lap[i] += ext[i];
+        }
         const float gyz = gyv[j] * gzv;
         float v[VEC], vv[VEC];
 #pragma unroll
@@ -675,8 +804,8 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
           }
         }
         if constexpr (ADJ) {
-          float lapF[VEC], im[VEC];
-          laplacian(qF, LF, cslot, s, j, lapF, X);
+          float lapF[VEC], im[VEC], laxF[3][VEC];
+          laplacian(qF, LF, cslot, s, j, lapF, X, laxF);
 #pragma unroll
           for (int i = 0; i < VEC; ++i) im[i] = fmaf(q[cslot][j][i], lapF[i], ic[j][i]);
           st_words<NF, kNT>(row_put<kF32, VEC>(im), rI, vrow_f[j], sz0f);
@@ -923,14 +1052,6 @@ struct Shell {
   }
 };
 
-// Slab index along an axis of n nodes with layers of W nodes, or -1.
-__device__ __forceinline__ int slab_index(int i, int n, int W) {
-  if (i < 0 || i >= n) return -1;
-  if (i < W) return i;
-  if (i >= n - W) return i - (n - 2 * W);
-  return -1;
-}
-
 // Per-axis addressing of one node: coordinate i along the axis, axis length
 // n, field stride, and the node's offset in the axis' slab array without its
 // slab index (plus the slab stride), 32-bit.
@@ -985,18 +1106,23 @@ __global__ void __launch_bounds__(256) cpml_psi_kernel(CpmlArgs c, const float *
   }
 }
 
-// One thread per node within W + R of a face.
+// One thread per node within W + R of a face, adding the terms of axes
+// a0 .. 2: a0 = 0 after the plain step (all nodes of the shell), a0 = 1 after
+// the step with the x part fused in (then only the z-layer planes and the
+// y-layer rows of the shell, count = its first two parts, need a term).
 __global__ void __launch_bounds__(256) cpml_fix_kernel(CpmlArgs c, const float *__restrict__ cur,
-                                                       const float *__restrict__ m, float *out) {
+                                                       const float *__restrict__ m, float *out, int a0,
+                                                       unsigned count) {
   const Shell S(c.W + R, c.nx, c.ny, c.nz);
   const unsigned t = blockIdx.x * 256u + threadIdx.x;
-  if (t >= S.count()) return;
+  if (t >= count) return;
   int x, y, z;
   S.node(t, x, y, z);
   const unsigned o = (static_cast<unsigned>(z) * c.ny + y) * c.nx + x;
   float extra = 0.f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
+    if (a < a0) continue;
     const AxisAt A = axis_at(c, a, x, y, z);
     if (A.i >= c.W + R && A.i < A.n - c.W - R) continue;  // psi_a and zeta_a vanish this far in
     float dpsi = 0.f;
@@ -1193,28 +1319,38 @@ constexpr Variant kVariants[] = {WAVE_VARIANTS(WAVE_VARIANT_INFO)};
 #undef WAVE_VARIANT_INFO
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ>
+// Shapes with the x part of the CPML boundary fused into the step: those
+// whose fused kernel fits the register file without spilling (at most two
+// rows per wavefront and four nodes per thread).
+template <int RY, int VEC>
+constexpr bool fuses_cpml() {
+  return RY <= 2 && RY * VEC <= 4;
+}
+
+template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ, bool CP = false>
 int blocks_per_cu() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void *>(step_kernel<S, BY, RY, PD, VEC, SEMI, ADJ>), 64 * BY, 0) !=
+          &nb, reinterpret_cast<const void *>(step_kernel<S, BY, RY, PD, VEC, SEMI, ADJ, CP>), 64 * BY, 0) !=
       hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
 template <int FAM, int S, int BY, int RY, int PD, int VEC, bool ADJ>
-int blocks_fam() {
+int blocks_fam(bool cpml) {
+  if constexpr (FAM == 0 && S == kF32 && !ADJ && fuses_cpml<RY, VEC>())
+    if (cpml) return blocks_per_cu<S, BY, RY, PD, VEC, false, false, true>();
   if constexpr (FAM == 0) return blocks_per_cu<S, BY, RY, PD, VEC, false, ADJ>();
-  if constexpr (FAM == 3 && S == kF32 && !ADJ) return blocks_per_cu<S, BY, RY, PD, VEC, true, false>();
+  if constexpr (FAM == 3 && S == kF32 && !ADJ) return blocks_per_cu<S, BY, RY, PD, VEC, true, false, false>();
   return 1;  // the 3D-blocked kernels size their grids from the block shape alone
 }
 
 template <int S, bool ADJ>
-int blocks_variant(int v) {
+int blocks_variant(int v, bool cpml) {
   switch (v) {
 #define WAVE_VARIANT_CASE(id, fam, by, ry, pd, vec) \
-  case id: return blocks_fam<fam, S, by, ry, pd, vec, ADJ>();
+  case id: return blocks_fam<fam, S, by, ry, pd, vec, ADJ>(cpml);
     WAVE_VARIANTS(WAVE_VARIANT_CASE)
 #undef WAVE_VARIANT_CASE
     default: return 1;
@@ -1225,11 +1361,18 @@ template <int FAM, int S, int BY, int RY, int PD, int VEC, bool ADJ>
 hipError_t launch_one(const StepArgs &a, hipStream_t s) {
   const unsigned grid = static_cast<unsigned>((a.total_tiles + 7) / 8 * 8);
   if constexpr (FAM == 0) {
-    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, ADJ>), dim3(grid), dim3(64 * BY), 0, s, a);
+    if constexpr (S == kF32 && !ADJ && fuses_cpml<RY, VEC>()) {
+      if (a.cpml) {
+        hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, false, true>), dim3(grid), dim3(64 * BY), 0, s,
+                           a);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, ADJ, false>), dim3(grid), dim3(64 * BY), 0, s, a);
   } else if constexpr (S != kF32 || ADJ) {
     return hipErrorInvalidValue;  // the study families are float32 forward only
   } else if constexpr (FAM == 3) {
-    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, true, false>), dim3(grid), dim3(64 * BY), 0, s, a);
+    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, true, false, false>), dim3(grid), dim3(64 * BY), 0, s, a);
   } else if constexpr (FAM == 1) {
     hipLaunchKernelGGL((gmem_kernel<BY, RY>), dim3(grid), dim3(64 * BY * RY), 0, s, a);
   } else {
@@ -1253,17 +1396,27 @@ hipError_t launch_variant(int v, const StepArgs &a, hipStream_t s) {
 
 int variant_count() { return kNumVariants; }
 
-int step_blocks_per_cu(int storage, int variant) {
+int step_blocks_per_cu(int storage, int variant, bool cpml) {
   if (variant < 0 || variant >= kNumVariants) return 1;
   switch (storage) {
-    case kF32: return blocks_variant<kF32, false>(variant);
-    case kF16: return blocks_variant<kF16, false>(variant);
-    case kBF16: return blocks_variant<kBF16, false>(variant);
+    case kF32: return blocks_variant<kF32, false>(variant, cpml);
+    case kF16: return blocks_variant<kF16, false>(variant, false);
+    case kBF16: return blocks_variant<kBF16, false>(variant, false);
     default: return 1;
   }
 }
 
 Variant variant_info(int v) { return kVariants[v]; }
+
+bool variant_fuses_cpml(int v) {
+  switch (v) {
+#define WAVE_VARIANT_CASE(id, fam, by, ry, pd, vec) \
+  case id: return fam == 0 && fuses_cpml<ry, vec>();
+    WAVE_VARIANTS(WAVE_VARIANT_CASE)
+#undef WAVE_VARIANT_CASE
+    default: return false;
+  }
+}
 
 hipError_t launch_step(int storage, int variant, bool adjoint, const StepArgs &a, hipStream_t s) {
   if (variant < 0 || variant >= kNumVariants) return hipErrorInvalidValue;
@@ -1372,10 +1525,12 @@ hipError_t launch_cpml_psi(const CpmlArgs &c, const float *cur, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_cpml_fix(const CpmlArgs &c, const float *cur, const float *m, float *out, hipStream_t s) {
-  const unsigned n = Shell(c.W + kRadius, c.nx, c.ny, c.nz).count();
+hipError_t launch_cpml_fix(const CpmlArgs &c, const float *cur, const float *m, float *out, bool yz_only,
+                           hipStream_t s) {
+  const Shell S(c.W + kRadius, c.nx, c.ny, c.nz);
+  const unsigned n = yz_only ? S.n0 + S.n1 : S.count();
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(cpml_fix_kernel, dim3((n + 255) / 256), dim3(256), 0, s, c, cur, m, out);
+  hipLaunchKernelGGL(cpml_fix_kernel, dim3((n + 255) / 256), dim3(256), 0, s, c, cur, m, out, yz_only ? 1 : 0, n);
   return hipGetLastError();
 }
 

@@ -55,6 +55,9 @@ int validate(const wave_params *p) {
     const int64_t shell = std::min(E2, nz) * ny * nx + mz * std::min(E2, ny) * nx + mz * my * std::min(E2, nx);
     if (shell >= (int64_t(1) << 31)) return WAVE_EINVAL;
     if (nx * ny * nz >= (int64_t(1) << 31)) return WAVE_EINVAL;  // 32-bit node offsets in the CPML kernels
+    // each psi / zeta slab array (2W x the cross-section) is one buffer resource
+    const int64_t cross = std::max(ny * nx, std::max(nz * nx, nz * ny));
+    if (4 * 2 * static_cast<int64_t>(W) * cross >= (int64_t(1) << 31)) return WAVE_EINVAL;
   }
   if (p->storage < WAVE_F32 || p->storage > WAVE_BF16) return WAVE_EINVAL;
   if (p->src[0] >= 0) {
@@ -185,6 +188,8 @@ struct Tiling {
 // float32 planes above 512 x 512, 8 x 4 rows of 2 nodes), else 2, else 1.
 int auto_variant(const wave_params *p) {
   const int64_t plane = static_cast<int64_t>(p->nx) * p->ny;
+  if (p->cpml_width > 0 && p->storage == WAVE_F32)  // shapes with the CPML terms fused into the step
+    return p->nx % 4 == 0 ? 12 : (p->nx % 2 == 0 ? 8 : 3);
   if (p->nx % 4 == 0) return (p->storage == WAVE_F32 && plane > (int64_t(1) << 18)) ? 11 : 12;
   if (p->nx % 2 == 0) return 8;
   return p->storage == WAVE_F32 ? 0 : 3;
@@ -216,7 +221,7 @@ Tiling make_tiling(const wave_params *p, int variant) {
     // as many long-lived workgroups as fit on the 256 CUs at once: long
     // z-chunks re-read fewer overlap planes and keep the prefetch pipeline full
     const int per_plane = t.tiles_x * t.tiles_y;
-    const int want = 256 * step_blocks_per_cu(p->storage, variant);
+    const int want = 256 * step_blocks_per_cu(p->storage, variant, p->cpml_width > 0);
     const int chunks = std::max(1, (want + per_plane / 2) / per_plane);
     zc = std::max(18, (nz + chunks - 1) / chunks);
     zc = (zc + 8) / 9 * 9;
@@ -250,6 +255,7 @@ struct wave_ctx {
   float *gx = nullptr, *gy = nullptr, *gz = nullptr, *m = nullptr, *grec = nullptr;
   int32_t *rz = nullptr;
   bool cpml = false;
+  bool cpml_fused = false;  // the forward shape's step kernel applies the x part of the CPML terms
   CpmlArgs cp{};
   int64_t *rec_lin = nullptr;
   void *fa = nullptr, *fb = nullptr, *fv = nullptr;
@@ -313,8 +319,15 @@ int enqueue_steps(wave_ctx *w, int count, const float *wavelet, float *traces, b
   StepArgs a = base_args(w, w->fwd);
   a.wavelet = wavelet;
   a.traces = traces;
-  // with CPML the receivers are sampled after the boundary correction
-  if (sample && w->fused_rec && !w->cpml) a.box = w->box;
+  // CPML: psi pass, step, correction pass (y and z parts only for the shapes
+  // whose step applies the x part itself); the receivers are gathered after
+  // the correction
+  const bool fix_pass = w->cpml;
+  if (w->cpml_fused) {
+    a.cpml = 1;
+    a.cp = w->cp;
+  }
+  if (sample && w->fused_rec && !fix_pass) a.box = w->box;
   for (int k = 0; k < count; ++k) {
     const int parity = (w->n + k) & 1;
     a.cur = w->field(parity);
@@ -325,11 +338,11 @@ int enqueue_steps(wave_ctx *w, int count, const float *wavelet, float *traces, b
     int rc = 0;
     if (w->cpml) rc = hip_rc(launch_cpml_psi(w->cp, static_cast<const float *>(a.cur), w->stream));
     if (!rc) rc = hip_rc(launch_step(w->p.storage, w->fwd.variant, false, a, w->stream));
-    if (!rc && w->cpml)
+    if (!rc && fix_pass)
       rc = hip_rc(launch_cpml_fix(w->cp, static_cast<const float *>(a.cur), w->m, static_cast<float *>(a.out),
-                                  w->stream));
+                                  w->cpml_fused, w->stream));
     if (rc) return rc;
-    if (sample && (!w->fused_rec || w->cpml) && w->p.nrec > 0) {
+    if (sample && (!w->fused_rec || fix_pass) && w->p.nrec > 0) {
       rc = hip_rc(launch_gather(w->p.storage, a.out, w->rec_lin, w->p.nrec, traces, w->st, k, w->stream));
       if (rc) return rc;
     }
@@ -417,6 +430,7 @@ int do_reset(wave_ctx *w) {
 // identical bits, so the choice only changes speed.
 struct TuneEntry {
   int nx, ny, nz, storage;
+  bool cpml;
   Tiling t;
 };
 std::mutex g_tune_mu;
@@ -427,8 +441,9 @@ int tune_forward(wave_ctx *w) {
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     for (const TuneEntry &e : g_tune_cache)
-      if (e.nx == p.nx && e.ny == p.ny && e.nz == p.nz && e.storage == p.storage) {
+      if (e.nx == p.nx && e.ny == p.ny && e.nz == p.nz && e.storage == p.storage && e.cpml == w->cpml) {
         w->fwd = e.t;
+        w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
         return WAVE_OK;
       }
   }
@@ -436,6 +451,7 @@ int tune_forward(wave_ctx *w) {
   for (int v = 0; v < variant_count(); ++v) {
     const Variant info = variant_info(v);
     if (info.family != 0 || p.nx % info.vec) continue;
+    if (w->cpml && !variant_fuses_cpml(v)) continue;
     wave_params q = p;
     q.variant = v;
     q.zchunk = 0;
@@ -456,6 +472,7 @@ int tune_forward(wave_ctx *w) {
   float best_ms = 3.0e38f;
   for (size_t i = 0; i < cands.size() && !rc; ++i) {
     w->fwd = cands[i];
+    w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
     rc = enqueue_steps(w, 1, nullptr, nullptr, false);
     if (!rc) rc = hip_rc(hipEventRecord(e0, w->stream));
     if (!rc) rc = enqueue_steps(w, 3, nullptr, nullptr, false);
@@ -470,11 +487,12 @@ int tune_forward(wave_ctx *w) {
   }
   w->p.src[0] = src_x;
   w->fwd = best;
+  w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (!rc) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune_cache.push_back(TuneEntry{p.nx, p.ny, p.nz, p.storage, best});
+    g_tune_cache.push_back(TuneEntry{p.nx, p.ny, p.nz, p.storage, w->cpml, best});
   }
   return rc;
 }
@@ -581,6 +599,9 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   // FP64 host tables
   const double ix2 = 1.0 / (p->dx * p->dx), iy2 = 1.0 / (p->dy * p->dy), iz2 = 1.0 / (p->dz * p->dz);
   w->c.k0 = static_cast<float>(kC[0] * (ix2 + iy2 + iz2));
+  w->c.k0a[0] = static_cast<float>(kC[0] * ix2);
+  w->c.k0a[1] = static_cast<float>(kC[0] * iy2);
+  w->c.k0a[2] = static_cast<float>(kC[0] * iz2);
   for (int m = 1; m <= 4; ++m) {
     w->c.kx[m - 1] = static_cast<float>(kC[m] * ix2);
     w->c.ky[m - 1] = static_cast<float>(kC[m] * iy2);
@@ -641,6 +662,7 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
     const double k0 = kC[0] * (ix2 + iy2 + iz2);
     w->gamma = static_cast<float>(Mmax * (std::fabs(k0) + kabs));
     if (!rc && p->cpml_width > 0) rc = setup_cpml(w, vmax);
+    w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
   }
   if (!rc && p->tune && p->variant == 0 && p->zchunk == 0) {
     rc = do_reset(w);  // zero fields (and CPML memory) for the timing runs

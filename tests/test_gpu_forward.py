@@ -174,7 +174,11 @@ def test_graph_replay_and_chunked_steps_are_bitwise_identical():
 
 
 @pytest.mark.parametrize("shape,src", [((1, 1, 1), (0, 0, 0)), ((1, 1, 9), (4, 0, 0)), ((6, 1, 1), (0, 0, 3)),
-                                       ((2, 3, 4), (3, 2, 1)), ((9, 70, 65), (64, 69, 8))])
+                                       ((2, 3, 4), (3, 2, 1)), ((9, 70, 65), (64, 69, 8)),
+                                       # 4 x nodes per lane: two active lanes; one row; a 4-column second tile
+                                       ((3, 2, 8), (5, 1, 1)), ((5, 1, 12), (11, 0, 2)), ((4, 9, 260), (258, 8, 0)),
+                                       # 2 x nodes per lane (nx even, not a multiple of 4)
+                                       ((7, 5, 18), (17, 4, 6))])
 def test_degenerate_and_edge_grids(shape, src):
     nz, ny, nx = shape
     vel = np.full(shape, 2500.0, dtype=np.float32)

@@ -1085,10 +1085,91 @@ __device__ __forceinline__ float cur_k(const float *cur, unsigned o, const AxisA
   return (j < 0 || j >= A.n) ? 0.f : cur[static_cast<int>(o) + k * static_cast<int>(A.stride)];
 }
 
-// One thread per node of the W-node layers.
-__global__ void __launch_bounds__(256) cpml_psi_kernel(CpmlArgs c, const float *__restrict__ cur) {
+// Row r of the shell's first two parts (the rows of its z-layer planes, then
+// its y-layer rows in the remaining planes) as (y, z).
+__device__ __forceinline__ void shell_row(const Shell &S, unsigned r, int &y, int &z) {
+  const unsigned r0 = S.cz * S.ny;
+  if (r < r0) {
+    const unsigned k = r / S.ny;
+    y = static_cast<int>(r - k * S.ny);
+    z = static_cast<int>(k < S.E ? k : S.nz - S.cz + k);
+    return;
+  }
+  r -= r0;
+  const unsigned k = r / S.cy, j = r - k * S.cy;
+  z = static_cast<int>(S.E + k);
+  y = static_cast<int>(j < S.E ? j : S.ny - S.cy + j);
+}
+
+template <int VEC> __device__ __forceinline__ void vload(const float *p, float *v) { lds_get<VEC>(p, v); }
+template <int VEC> __device__ __forceinline__ void vstore(float *p, const float *v) { lds_put<VEC>(p, v); }
+
+// psi_a update over the rows of the first two parts of the W-node shell, VEC
+// consecutive x nodes per thread (nx % VEC == 0): the y and z axes where the
+// row lies in their layers (whole rows), the x axis for the nodes of the row
+// in the x layers.
+template <int VEC>
+__global__ void __launch_bounds__(256) cpml_psi_rows_kernel(CpmlArgs c, const float *__restrict__ cur) {
   const Shell S(c.W, c.nx, c.ny, c.nz);
+  const unsigned qx = static_cast<unsigned>(c.nx) / VEC;
   const unsigned t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= (S.cz * S.ny + S.mz * S.cy) * qx) return;
+  const unsigned r = t / qx;
+  const int x = static_cast<int>((t - r * qx) * VEC);
+  int y, z;
+  shell_row(S, r, y, z);
+  const unsigned nx = c.nx, ny = c.ny, W2 = 2u * c.W;
+  const unsigned o = (static_cast<unsigned>(z) * ny + y) * nx + x;
+#pragma unroll
+  for (int a = 1; a < 3; ++a) {
+    const int i = a == 1 ? y : z, n = a == 1 ? c.ny : c.nz;
+    const int s = slab_index(i, n, c.W);
+    if (s < 0) continue;
+    const unsigned stride = a == 1 ? nx : nx * ny;
+    float d[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) d[e] = 0.f;
+#pragma unroll
+    for (int m = 1; m <= R; ++m) {
+      float up[VEC], dn[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) up[e] = dn[e] = 0.f;
+      if (i + m < n) vload<VEC>(cur + o + m * stride, up);
+      if (i - m >= 0) vload<VEC>(cur + o - m * stride, dn);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) d[e] = fmaf(c.d1w[a][m - 1], up[e] - dn[e], d[e]);
+    }
+    float *ps = c.psi[a] + (a == 1 ? (static_cast<unsigned>(z) * W2 + s) * nx : (s * ny + static_cast<unsigned>(y)) * nx) + x;
+    float pv[VEC];
+    vload<VEC>(ps, pv);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) pv[e] = fmaf(c.cb[a][i], pv[e], c.ca[a][i] * d[e]);
+    vstore<VEC>(ps, pv);
+  }
+  if (x < c.W || x + VEC - 1 >= c.nx - c.W) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int xe = x + e;
+      const int s = slab_index(xe, c.nx, c.W);
+      if (s < 0) continue;
+      float d = 0.f;
+#pragma unroll
+      for (int m = 1; m <= R; ++m) {
+        const float up = xe + m < c.nx ? cur[o + e + m] : 0.f;
+        const float dn = xe - m >= 0 ? cur[o + e - m] : 0.f;
+        d = fmaf(c.d1w[0][m - 1], up - dn, d);
+      }
+      float *ps = c.psi[0] + (static_cast<unsigned>(z) * ny + y) * W2 + s;
+      *ps = fmaf(c.cb[0][xe], *ps, c.ca[0][xe] * d);
+    }
+  }
+}
+
+// One thread per node of the W-node shell from node t0 on (the x-layer
+// columns of its third part, after cpml_psi_rows_kernel; or all of it).
+__global__ void __launch_bounds__(256) cpml_psi_kernel(CpmlArgs c, const float *__restrict__ cur, unsigned t0) {
+  const Shell S(c.W, c.nx, c.ny, c.nz);
+  const unsigned t = t0 + blockIdx.x * 256u + threadIdx.x;
   if (t >= S.count()) return;
   int x, y, z;
   S.node(t, x, y, z);
@@ -1104,6 +1185,89 @@ __global__ void __launch_bounds__(256) cpml_psi_kernel(CpmlArgs c, const float *
     float *ps = c.psi[a] + A.slab_rest + static_cast<unsigned>(s) * A.slab_stride;
     *ps = fmaf(c.cb[a][A.i], *ps, c.ca[a][A.i] * d);
   }
+}
+
+// The y and z terms after the step with the x part fused in:
+// out += m * sum_{a = y, z} (D1_a psi_a + zeta_a), zeta_a updated, over the
+// rows of the first two parts of the (W + R)-node shell (the other nodes get
+// no y or z term), VEC consecutive x nodes per thread (nx % VEC == 0).  Per
+// node the same operations as cpml_fix_kernel with a0 = 1.
+template <int VEC>
+__global__ void __launch_bounds__(256) cpml_fix_yz_kernel(CpmlArgs c, const float *__restrict__ cur,
+                                                          const float *__restrict__ m, float *out) {
+  const Shell S(c.W + R, c.nx, c.ny, c.nz);
+  const unsigned qx = static_cast<unsigned>(c.nx) / VEC;
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= (S.cz * S.ny + S.mz * S.cy) * qx) return;
+  const unsigned r = t / qx;
+  const int x = static_cast<int>((t - r * qx) * VEC);
+  int y, z;
+  shell_row(S, r, y, z);
+  const unsigned nx = c.nx, ny = c.ny, W2 = 2u * c.W;
+  const unsigned o = (static_cast<unsigned>(z) * ny + y) * nx + x;
+  float extra[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) extra[e] = 0.f;
+#pragma unroll
+  for (int a = 1; a < 3; ++a) {
+    const int i = a == 1 ? y : z, n = a == 1 ? c.ny : c.nz;
+    if (i >= c.W + R && i < n - c.W - R) continue;  // psi_a and zeta_a vanish this far in
+    const unsigned stride = a == 1 ? nx : nx * ny;
+    // slab element of slab index s: y: (z, s, x), z: (s, y, x)
+    auto slab = [&](int sidx) {
+      return a == 1 ? (static_cast<unsigned>(z) * W2 + static_cast<unsigned>(sidx)) * nx + x
+                    : (static_cast<unsigned>(sidx) * ny + static_cast<unsigned>(y)) * nx + x;
+    };
+    float dpsi[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) dpsi[e] = 0.f;
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+      float pp[VEC], pm[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) pp[e] = pm[e] = 0.f;
+      const int sp = slab_index(i + k, n, c.W), sm = slab_index(i - k, n, c.W);
+      if (sp >= 0) vload<VEC>(c.psi[a] + slab(sp), pp);
+      if (sm >= 0) vload<VEC>(c.psi[a] + slab(sm), pm);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) dpsi[e] = fmaf(c.d1w[a][k - 1], pp[e] - pm[e], dpsi[e]);
+    }
+    const int s = slab_index(i, n, c.W);
+    if (s < 0) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) extra[e] += dpsi[e];
+      continue;
+    }
+    float cc[VEC], d2[VEC];
+    vload<VEC>(cur + o, cc);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) d2[e] = c.d2w[a][0] * cc[e];
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+      float up[VEC], dn[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) up[e] = dn[e] = 0.f;
+      if (i + k < n) vload<VEC>(cur + o + k * stride, up);
+      if (i - k >= 0) vload<VEC>(cur + o - k * stride, dn);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) d2[e] = fmaf(c.d2w[a][k], up[e] + dn[e], d2[e]);
+    }
+    float *ze = c.zeta[a] + slab(s);
+    float zv[VEC];
+    vload<VEC>(ze, zv);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      zv[e] = fmaf(c.cb[a][i], zv[e], c.ca[a][i] * (d2[e] + dpsi[e]));
+      extra[e] += dpsi[e] + zv[e];
+    }
+    vstore<VEC>(ze, zv);
+  }
+  float mv[VEC], ov[VEC];
+  vload<VEC>(m + o, mv);
+  vload<VEC>(out + o, ov);
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) ov[e] = fmaf(mv[e], extra[e], ov[e]);
+  vstore<VEC>(out + o, ov);
 }
 
 // One thread per node within W + R of a face, adding the terms of axes
@@ -1519,18 +1683,36 @@ hipError_t launch_grad_final(const float *img, const float *m, float dt, float *
 }
 
 hipError_t launch_cpml_psi(const CpmlArgs &c, const float *cur, hipStream_t s) {
-  const unsigned n = Shell(c.W, c.nx, c.ny, c.nz).count();
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(cpml_psi_kernel, dim3((n + 255) / 256), dim3(256), 0, s, c, cur);
+  const Shell S(c.W, c.nx, c.ny, c.nz);
+  const int vec = c.nx % 4 == 0 ? 4 : (c.nx % 2 == 0 ? 2 : 1);
+  const unsigned nrow = (S.cz * S.ny + S.mz * S.cy) * (static_cast<unsigned>(c.nx) / vec);
+  if (nrow > 0) {
+    const dim3 g((nrow + 255) / 256), b(256);
+    if (vec == 4) hipLaunchKernelGGL(cpml_psi_rows_kernel<4>, g, b, 0, s, c, cur);
+    else if (vec == 2) hipLaunchKernelGGL(cpml_psi_rows_kernel<2>, g, b, 0, s, c, cur);
+    else hipLaunchKernelGGL(cpml_psi_rows_kernel<1>, g, b, 0, s, c, cur);
+  }
+  if (S.n2 > 0)
+    hipLaunchKernelGGL(cpml_psi_kernel, dim3((S.n2 + 255) / 256), dim3(256), 0, s, c, cur, S.n0 + S.n1);
   return hipGetLastError();
 }
 
 hipError_t launch_cpml_fix(const CpmlArgs &c, const float *cur, const float *m, float *out, bool yz_only,
                            hipStream_t s) {
   const Shell S(c.W + kRadius, c.nx, c.ny, c.nz);
-  const unsigned n = yz_only ? S.n0 + S.n1 : S.count();
+  if (yz_only) {
+    const int vec = c.nx % 4 == 0 ? 4 : (c.nx % 2 == 0 ? 2 : 1);
+    const unsigned n = (S.cz * S.ny + S.mz * S.cy) * (static_cast<unsigned>(c.nx) / vec);
+    if (n == 0) return hipSuccess;
+    const dim3 g((n + 255) / 256), b(256);
+    if (vec == 4) hipLaunchKernelGGL(cpml_fix_yz_kernel<4>, g, b, 0, s, c, cur, m, out);
+    else if (vec == 2) hipLaunchKernelGGL(cpml_fix_yz_kernel<2>, g, b, 0, s, c, cur, m, out);
+    else hipLaunchKernelGGL(cpml_fix_yz_kernel<1>, g, b, 0, s, c, cur, m, out);
+    return hipGetLastError();
+  }
+  const unsigned n = S.count();
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(cpml_fix_kernel, dim3((n + 255) / 256), dim3(256), 0, s, c, cur, m, out, yz_only ? 1 : 0, n);
+  hipLaunchKernelGGL(cpml_fix_kernel, dim3((n + 255) / 256), dim3(256), 0, s, c, cur, m, out, 0, n);
   return hipGetLastError();
 }
 

@@ -184,6 +184,7 @@ def precision_leg(nt: int = 500) -> dict:
         print(f"[bench] precision 1024^3 {fmt}: {out[fmt]}", file=sys.stderr, flush=True)
     del vel
     torch.cuda.empty_cache()
+    out["stream_ceiling"] = stream_ceiling(dev, W.npts)  # plain torch streams of the 1024^3 size
     return out
 
 
@@ -331,6 +332,8 @@ def main():
                     help="requests of the Poisson shot stream to serve after the throughput run (0: skip)")
     ap.add_argument("--study-only", action="store_true",
                     help="run only the 1024^3 kernel study (3D gmem/smem vs 2.5D shapes) and print its JSON")
+    ap.add_argument("--cpml-only", action="store_true",
+                    help="run only the 512^3 CPML leg (fused and unfused shapes) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -352,6 +355,10 @@ def main():
         return
     dev = torch.device("cuda:0")
     W = workload("large")
+    if args.cpml_only:
+        v_dev = torch.from_numpy(W.velocity()).to(dev)
+        print(json.dumps({"cpml_512": cpml_leg(W, v_dev, min(args.nt or W.nt, 200))}), flush=True)
+        return
     nt = args.nt or W.nt
     print(f"[bench] building {W.name} inputs", file=sys.stderr, flush=True)
     vel = W.velocity()

@@ -105,6 +105,12 @@ typedef struct {
   double cpml_reflection;    /* CPML target reflection coefficient R in (0, 1] (default 1e-3):
                                 d(xi) = -3 v_max ln(R) xi^2 / (2 W h) */
   double cpml_f0;            /* CPML frequency shift alpha(xi) = pi f0 (1 - xi), Hz (default 0) */
+  int32_t cache_hint;        /* cache policy of the fields the float32 step reads or writes once
+                                (A^{n-1}, m, A^{n+1}): 0 = nontemporal, so that the cache keeps
+                                A^n's halo planes (with tune = 1 the regular policy is timed too);
+                                1 = regular, for grids whose fields fit the 256 MB last-level
+                                cache.  1 needs float32 storage, no CPML and a 2.5D variant.
+                                Results are the same bits either way */
 } wave_params;
 
 /* Fill `p` with defaults: no source, no receivers, float32 storage,

@@ -46,6 +46,7 @@ class WaveParams(ctypes.Structure):
         ("cpml_width", ctypes.c_int32),
         ("cpml_reflection", ctypes.c_double),
         ("cpml_f0", ctypes.c_double),
+        ("cache_hint", ctypes.c_int32),
     ]
 
 

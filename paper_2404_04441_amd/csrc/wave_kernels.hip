@@ -270,7 +270,11 @@ static_assert(kPadZ >= (kQ - 1) + kMaxPD + R, "z padding must cover the last tri
 // lanes' values).  The y and z parts follow in cpml_fix_kernel over the rows
 // and planes within W + R of a y or z face: in the streaming kernel their
 // neighbours would be loads the z loop waits on in every such row and plane.
-template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ, bool CP>
+// KEEP: A^{n-1}, m and A^{n+1} use the regular cache policy instead of the
+// nontemporal one, so that a grid whose fields fit the last-level cache stays
+// there from step to step (float32 forward; chosen by create-time tuning or
+// the caller).
+template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ, bool CP, bool KEEP>
 __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   using C = Codec<S>;
   using StageT = Stage<S, RY, VEC, (2 * R + BY - 1) / BY, ADJ, CP>;
@@ -287,6 +291,8 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   static_assert(VEC == 1 || VEC == 2 || VEC == 4, "lane width");
   static_assert(!(SEMI && ADJ), "the semi-stencil form is forward only");
   static_assert(!CP || (S == kF32 && !SEMI && !ADJ), "the fused CPML step is float32 forward");
+  static_assert(!KEEP || (S == kF32 && !SEMI && !ADJ && !CP), "the cached policy is for the plain float32 step");
+  constexpr int NTP = KEEP ? 0 : kNT;  // cache policy of the fields read or written once
   // each LDS plane ends with a scratch row: halo writes of lanes or
   // wavefronts with nothing to write go there, so no write is predicated
   constexpr int LP = LH * LW + 64 * VEC;
@@ -496,8 +502,8 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       st.lead[j] = ld_words<NA, 0>(rU, vrow[j], sl);
-      st.p[j] = ld_words<NA, kNT>(rP, vrow[j], sc);
-      st.m[j] = ld_words<NF, kNT>(rM, vrow_f[j], scf);
+      st.p[j] = ld_words<NA, NTP>(rP, vrow[j], sc);
+      st.m[j] = ld_words<NF, NTP>(rM, vrow_f[j], scf);
     }
 #pragma unroll
     for (int i = 0; i < NYH; ++i) st.yh[i] = ld_words<NA, 0>(rU, vyh[i], sc);
@@ -782,7 +788,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
           }
         }
         if (S == kF32) {
-          st_words<NA, kNT>(row_put<S, VEC>(v), rO, vrow[j], sz0);
+          st_words<NA, NTP>(row_put<S, VEC>(v), rO, vrow[j], sz0);
 #pragma unroll
           for (int i = 0; i < VEC; ++i) outv[j][i] = v[i];
         } else {
@@ -1495,7 +1501,7 @@ template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ, bool CP =
 int blocks_per_cu() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void *>(step_kernel<S, BY, RY, PD, VEC, SEMI, ADJ, CP>), 64 * BY, 0) !=
+          &nb, reinterpret_cast<const void *>(step_kernel<S, BY, RY, PD, VEC, SEMI, ADJ, CP, false>), 64 * BY, 0) !=
       hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
@@ -1527,16 +1533,25 @@ hipError_t launch_one(const StepArgs &a, hipStream_t s) {
   if constexpr (FAM == 0) {
     if constexpr (S == kF32 && !ADJ && fuses_cpml<RY, VEC>()) {
       if (a.cpml) {
-        hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, false, true>), dim3(grid), dim3(64 * BY), 0, s,
-                           a);
+        hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, false, true, false>), dim3(grid), dim3(64 * BY),
+                           0, s, a);
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, ADJ, false>), dim3(grid), dim3(64 * BY), 0, s, a);
+    if constexpr (S == kF32 && !ADJ) {
+      if (a.keep) {
+        hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, false, false, true>), dim3(grid), dim3(64 * BY),
+                           0, s, a);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, ADJ, false, false>), dim3(grid), dim3(64 * BY), 0, s,
+                       a);
   } else if constexpr (S != kF32 || ADJ) {
     return hipErrorInvalidValue;  // the study families are float32 forward only
   } else if constexpr (FAM == 3) {
-    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, true, false, false>), dim3(grid), dim3(64 * BY), 0, s, a);
+    hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, true, false, false, false>), dim3(grid), dim3(64 * BY), 0, s,
+                       a);
   } else if constexpr (FAM == 1) {
     hipLaunchKernelGGL((gmem_kernel<BY, RY>), dim3(grid), dim3(64 * BY * RY), 0, s, a);
   } else {

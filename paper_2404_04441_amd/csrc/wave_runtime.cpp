@@ -82,6 +82,11 @@ int validate(const wave_params *p) {
   }
   if (p->zchunk < 0 || p->graph_steps < 0) return WAVE_EINVAL;
   if (p->tune < 0 || p->tune > 1) return WAVE_EINVAL;
+  // the cached policy exists for the float32 2.5D forward kernels without CPML
+  if (p->cache_hint < 0 || p->cache_hint > 1) return WAVE_EINVAL;
+  if (p->cache_hint == 1 &&
+      (p->storage != WAVE_F32 || p->cpml_width > 0 || (p->variant > 0 && variant_info(p->variant).family != 0)))
+    return WAVE_EINVAL;
   return WAVE_OK;
 }
 
@@ -181,6 +186,7 @@ bool detect_box(const std::vector<int32_t> &rec, int nrec, RecBox *b) {
 // One tile decomposition of the grid for a step-kernel variant.
 struct Tiling {
   int variant = 0, tiles_x = 0, tiles_y = 0, nchunks = 0, zchunk = 0, total_tiles = 0;
+  bool keep = false;  // float32 forward: regular cache policy for the fields streamed once
 };
 
 // Measured-best tile shapes on MI355X (variant indices of the kernel
@@ -302,6 +308,7 @@ StepArgs base_args(const wave_ctx *w, const Tiling &t) {
   a.nchunks = t.nchunks;
   a.zchunk = t.zchunk;
   a.total_tiles = t.total_tiles;
+  a.keep = t.keep ? 1 : 0;
   a.c = w->c;
   a.sx = w->p.src[0] >= 0 ? w->p.src[0] : -1;
   a.sy = w->p.src[1];
@@ -429,7 +436,7 @@ int do_reset(wave_ctx *w) {
 // steps on the zeroed fields and keep the fastest.  All candidates compute
 // identical bits, so the choice only changes speed.
 struct TuneEntry {
-  int nx, ny, nz, storage;
+  int nx, ny, nz, storage, cache_hint;
   bool cpml;
   Tiling t;
 };
@@ -441,7 +448,8 @@ int tune_forward(wave_ctx *w) {
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     for (const TuneEntry &e : g_tune_cache)
-      if (e.nx == p.nx && e.ny == p.ny && e.nz == p.nz && e.storage == p.storage && e.cpml == w->cpml) {
+      if (e.nx == p.nx && e.ny == p.ny && e.nz == p.nz && e.storage == p.storage && e.cpml == w->cpml &&
+          e.cache_hint == p.cache_hint) {
         w->fwd = e.t;
         w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
         return WAVE_OK;
@@ -460,6 +468,19 @@ int tune_forward(wave_ctx *w) {
       q.zchunk = zc;
       const Tiling t = make_tiling(&q, v);
       if (zc < p.nz && t.zchunk != cands.back().zchunk) cands.push_back(t);
+    }
+  }
+  // float32 without CPML: every candidate also with the cached policy
+  // (cache_hint 0), or only with it (cache_hint 1)
+  if (p.storage == WAVE_F32 && !w->cpml) {
+    const size_t n = cands.size();
+    for (size_t i = 0; i < n; ++i) {
+      Tiling t = cands[i];
+      t.keep = true;
+      if (p.cache_hint == 1)
+        cands[i] = t;
+      else
+        cands.push_back(t);
     }
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -492,7 +513,7 @@ int tune_forward(wave_ctx *w) {
   if (e1) (void)hipEventDestroy(e1);
   if (!rc) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune_cache.push_back(TuneEntry{p.nx, p.ny, p.nz, p.storage, w->cpml, best});
+    g_tune_cache.push_back(TuneEntry{p.nx, p.ny, p.nz, p.storage, p.cache_hint, w->cpml, best});
   }
   return rc;
 }
@@ -629,6 +650,7 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   // tiling: the forward step and (for adjoint contexts) the adjoint step
   // each get a shape; variant 0 picks the measured-best ones
   w->fwd = make_tiling(p, p->variant > 0 ? p->variant : auto_variant(p));
+  w->fwd.keep = p->cache_hint == 1;
   if (p->adjoint) w->adj = make_tiling(p, p->variant > 0 ? p->variant : kAdjointVariant);
 
   StepState init{};

@@ -36,12 +36,15 @@ class Solver:
     variant, zchunk, graph_steps : kernel tiling / replay options
     tune : time the candidate tile shapes at create and keep the fastest (cached per grid shape)
     cpml_width, cpml_reflection, cpml_f0 : CPML absorbing layers (float32 forward; sponge_width must be 0)
+    cache_hint : 1 = keep A^{n-1}, m, A^{n+1} cacheable (float32 grids that fit the last-level cache);
+                 0 = nontemporal (tune also times the cacheable policy)
     """
 
     def __init__(self, vel: torch.Tensor, h, dt: float, src=None, rec=None, sponge_width: int = 0,
                  sponge_alpha: float = 0.015, storage: str = "f32", adjoint: bool = False, nt_max: int = 0,
                  ckpt_interval: int = 0, variant: int = 0, zchunk: int = 0, graph_steps: int = 0, tune: bool = False,
-                 cpml_width: int = 0, cpml_reflection: float = 1e-3, cpml_f0: float = 0.0, stream=None):
+                 cpml_width: int = 0, cpml_reflection: float = 1e-3, cpml_f0: float = 0.0, cache_hint: int = 0,
+                 stream=None):
         lib = L.lib()
         _dev_f32(vel, "vel")
         nz, ny, nx = vel.shape
@@ -63,6 +66,7 @@ class Solver:
         p.variant, p.zchunk, p.graph_steps = int(variant), int(zchunk), int(graph_steps)
         p.tune = 1 if tune else 0
         p.cpml_width, p.cpml_reflection, p.cpml_f0 = int(cpml_width), float(cpml_reflection), float(cpml_f0)
+        p.cache_hint = int(cache_hint)
         nbytes = ctypes.c_size_t()
         L.check(lib.wave_workspace_bytes(ctypes.byref(p), ctypes.byref(nbytes)), "wave_workspace_bytes")
         self.workspace_bytes = nbytes.value

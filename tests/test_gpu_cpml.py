@@ -88,6 +88,9 @@ def test_cpml_shapes_and_replay():
             e_u, e_t = oracle.rel_l2(got["u"], ref["u"]), oracle.rel_l2(got["traces"], ref["traces"])
             assert e_u <= TOL and e_t <= TOL, (v, e_u, e_t)
     assert nfused >= 3
+    _say("case: CPML with create-time tuning (fused shapes only)")
+    got = _gpu(vel, h, dt, wav, rec, src, W, nt, tune=1)
+    assert np.array_equal(got["u"], base["u"]) and np.array_equal(got["traces"], base["traces"])
     _say("case: CPML graph replay")
     got = _gpu(vel, h, dt, wav, rec, src, W, nt, graph_steps=6)
     assert np.array_equal(got["u"], base["u"]) and np.array_equal(got["traces"], base["traces"])

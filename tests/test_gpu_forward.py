@@ -134,6 +134,10 @@ def test_tiling_variants_and_zchunks_are_bitwise_identical():
                 continue
             assert np.array_equal(got["u"], base["u"]), (v, zc)
             assert np.array_equal(got["traces"], base["traces"]), (v, zc)
+            if variant_info(v)["family"] == 0 and zc == 0:  # the cached policy: same bits
+                got = gpu_run(vel2, h, dt, src, wav, rec2, nt, sponge_width=5, sponge_alpha=0.05, variant=v,
+                              cache_hint=1)
+                assert np.array_equal(got["u"], base["u"]) and np.array_equal(got["traces"], base["traces"]), v
 
 
 def test_tuned_shape_is_bitwise_identical():
@@ -145,6 +149,9 @@ def test_tuned_shape_is_bitwise_identical():
         _say(f"case: tune=True nx={nx}")
         base = gpu_run(v, h, dt, src, wav, r, nt, sponge_width=5, sponge_alpha=0.05)
         got = gpu_run(v, h, dt, src, wav, r, nt, sponge_width=5, sponge_alpha=0.05, tune=True)
+        assert np.array_equal(got["u"], base["u"]) and np.array_equal(got["traces"], base["traces"])
+        _say(f"case: tune=True cache_hint=1 nx={nx}")
+        got = gpu_run(v, h, dt, src, wav, r, nt, sponge_width=5, sponge_alpha=0.05, tune=True, cache_hint=1)
         assert np.array_equal(got["u"], base["u"]) and np.array_equal(got["traces"], base["traces"])
 
 

@@ -89,9 +89,11 @@ typedef struct {
                                 workgroup's buffers span < 2 GiB; 0 = chosen from the grid size */
   int32_t graph_steps;       /* >0: replay steps from a captured HIP graph of this many steps */
   int32_t tune;              /* 1 with variant = 0 and zchunk = 0: wave_create times the candidate
-                                2.5D shapes and z-chunks for a few steps on the fresh (zero) fields
-                                and keeps the fastest; the choice is cached per (nx, ny, nz,
-                                storage, CPML or not) for the life of the process.  Every
+                                2.5D shapes and z-chunks (float32: both cache policies; float32
+                                forward without CPML or adjoint: also the 3D-blocked gmem and
+                                smem shapes) for a few steps on the fresh (zero) fields and
+                                keeps the fastest; the choice is cached per (nx, ny, nz, storage,
+                                CPML or not, cache_hint) for the life of the process.  Every
                                 choice computes the same bits.  0: the fixed automatic rule */
   int32_t cpml_width;        /* >0: CPML absorbing layers of this many nodes on all six faces (the
                                 boundary of paper Sec. II / IV-A; float32, forward only, needs

@@ -456,8 +456,15 @@ int tune_forward(wave_ctx *w) {
       }
   }
   std::vector<Tiling> cands;
-  for (int v = 0; v < variant_count(); ++v) {
+  // the 3D-blocked families compute the same bits as the 2.5D shapes (float32
+  // forward); on small grids, where everything stays in cache, they can win
+  const bool blocked_ok = p.storage == WAVE_F32 && !w->cpml && !p.adjoint && p.cache_hint == 0;
+  for (int v = 1; v < variant_count(); ++v) {
     const Variant info = variant_info(v);
+    if ((info.family == 1 || info.family == 2) && blocked_ok) {
+      cands.push_back(make_tiling(&p, v));
+      continue;
+    }
     if (info.family != 0 || p.nx % info.vec) continue;
     if (w->cpml && !variant_fuses_cpml(v)) continue;
     wave_params q = p;
@@ -475,6 +482,7 @@ int tune_forward(wave_ctx *w) {
   if (p.storage == WAVE_F32 && !w->cpml) {
     const size_t n = cands.size();
     for (size_t i = 0; i < n; ++i) {
+      if (variant_info(cands[i].variant).family != 0) continue;
       Tiling t = cands[i];
       t.keep = true;
       if (p.cache_hint == 1)

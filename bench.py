@@ -324,8 +324,9 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
-    ap.add_argument("--tune", action="store_true",
-                    help="create-time tuning of the tile shape, z-chunk and cache policy (outside the timed region)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="the fixed tile-shape rule instead of create-time tuning (shape, z-chunk, cache policy; "
+                         "outside the timed region)")
     ap.add_argument("--nt", type=int, default=0, help="time steps per shot (default: the workload's 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
@@ -367,7 +368,7 @@ def main():
     wav = torch.from_numpy(W.wavelet(nt)).to(dev)
     s = Solver(torch.from_numpy(vel).to(dev), W.h, W.dt, src=W.src, rec=W.rec, sponge_width=W.sponge_width,
                sponge_alpha=W.sponge_alpha, storage=args.storage, variant=args.variant, zchunk=args.zchunk,
-               tune=args.tune)
+               tune=not args.no_tune)
     traces = torch.empty((nt, len(W.rec)), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
@@ -430,7 +431,7 @@ def main():
         "config": {"workload": f"{W.name} FP32 fused forward shot: 8th-order star stencil, leapfrog, "
                                f"20-node sponge, Ricker source at (256,256,10), 512x512 receiver plane z=0",
                    "grid": list(W.shape[::-1]), "time_steps": nt, "storage": args.storage,
-                   "variant": args.variant, "zchunk": args.zchunk, "tuned": bool(args.tune)},
+                   "variant": args.variant, "zchunk": args.zchunk, "tuned": not args.no_tune},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.storage),
                      "kernel": "step_kernel", "kernel_ms": round(kernel_ms, 4),

@@ -88,13 +88,14 @@ typedef struct {
   int32_t zchunk;            /* z-planes per workgroup, rounded up to a multiple of 9 and capped so a
                                 workgroup's buffers span < 2 GiB; 0 = chosen from the grid size */
   int32_t graph_steps;       /* >0: replay steps from a captured HIP graph of this many steps */
-  int32_t tune;              /* 1 with variant = 0 and zchunk = 0: wave_create times the candidate
+  int32_t tune;              /* 1 (the default) with variant = 0 and zchunk = 0: wave_create times the candidate
                                 2.5D shapes and z-chunks (float32: both cache policies; float32
                                 forward without CPML or adjoint: also the 3D-blocked gmem and
                                 smem shapes) for a few steps on the fresh (zero) fields and
                                 keeps the fastest; the choice is cached per (nx, ny, nz, storage,
                                 CPML or not, cache_hint) for the life of the process.  Every
-                                choice computes the same bits.  0: the fixed automatic rule */
+                                choice computes the same bits; wave_tiling reports it.  0: the
+                                fixed automatic rule (measured: 30-50% slower at some sizes) */
   int32_t cpml_width;        /* >0: CPML absorbing layers of this many nodes on all six faces (the
                                 boundary of paper Sec. II / IV-A; float32, forward only, needs
                                 sponge_width = 0, 2*cpml_width <= nx, ny, nz, nx*ny*nz < 2^31 and
@@ -116,7 +117,7 @@ typedef struct {
 } wave_params;
 
 /* Fill `p` with defaults: no source, no receivers, float32 storage,
- * alpha 0.015, unit spacings and dt (callers set the grid and dt). */
+ * alpha 0.015, unit spacings and dt (callers set the grid and dt), tune = 1. */
 void wave_params_init(wave_params *p);
 
 /* Bytes of device workspace wave_create needs for `p`: m = (v dt)^2, the
@@ -180,6 +181,15 @@ int wave_read_field(wave_t w, int32_t which, float *out_dev);
 
 /* Host copy of the step counter n (steps since the last reset). */
 int wave_time_index(wave_t w, int32_t *n);
+
+/* The forward step configuration wave_create settled on (after tuning, if
+ * asked), written to out[0..2] (caller-owned host array of 3): the kernel
+ * variant (1 .. wave_variant_count()-1; see wave_variant_info), the z-chunk
+ * in planes, and the cache policy (0 nontemporal, 1 regular; see
+ * cache_hint).  Passing these back as variant, zchunk and cache_hint (with
+ * tune = 0) reproduces the configuration.  Errors: WAVE_EINVAL for a null
+ * argument. */
+int wave_tiling(wave_t w, int32_t *out);
 
 /* Shot snapshots: the complete state of a forward run after its last
  * enqueued step (step counter, both stored time levels -- A^n and A^{n-1}, or

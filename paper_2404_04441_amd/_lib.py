@@ -20,7 +20,7 @@ STORAGE = {"f32": WAVE_F32, "f16": WAVE_F16, "bf16": WAVE_BF16}
 EXPORTS = (
     "wave_params_init", "wave_workspace_bytes", "wave_create", "wave_reset", "wave_step", "wave_run",
     "wave_adjoint", "wave_read_field", "wave_time_index", "wave_state_bytes", "wave_save_state", "wave_load_state",
-    "wave_sync_status", "wave_destroy",
+    "wave_sync_status", "wave_destroy", "wave_tiling",
     "wave_variant_count", "wave_variant_info", "wave_status_string",
 )
 
@@ -83,6 +83,7 @@ def lib():
         L.wave_save_state.argtypes = [vp, vp]
         L.wave_load_state.argtypes = [vp, vp]
         L.wave_sync_status.argtypes = [vp, P(u32)]
+        L.wave_tiling.argtypes = [vp, P(i32)]
         L.wave_destroy.argtypes = [vp]
         L.wave_variant_count.argtypes = []
         L.wave_variant_info.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]

@@ -581,6 +581,7 @@ void wave_params_init(wave_params *p) {
   p->cpml_reflection = 1e-3;
   p->storage = WAVE_F32;
   p->src[0] = -1;
+  p->tune = 1;
 }
 
 int wave_workspace_bytes(const wave_params *p, size_t *bytes) {
@@ -934,6 +935,21 @@ int wave_destroy(wave_t w) {
 }
 
 int wave_variant_count(void) { return variant_count(); }
+
+int wave_tiling(wave_t w, int32_t *out) {
+  if (!w || !out) return WAVE_EINVAL;
+  // variant 0 (automatic) runs its fallback shape: report the explicit
+  // variant with that shape
+  int v = w->fwd.variant;
+  for (int k = 1; v == 0 && k < variant_count(); ++k) {
+    const Variant a = variant_info(0), b = variant_info(k);
+    if (a.family == b.family && a.by == b.by && a.ry == b.ry && a.pd == b.pd && a.vec == b.vec) v = k;
+  }
+  out[0] = v;
+  out[1] = w->fwd.zchunk;
+  out[2] = w->fwd.keep ? 1 : 0;
+  return WAVE_OK;
+}
 
 int wave_variant_info(int32_t variant, int32_t *info) {
   if (!info || variant < 0 || variant >= variant_count()) return WAVE_EINVAL;

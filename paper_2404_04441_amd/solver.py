@@ -34,7 +34,8 @@ class Solver:
     storage  : "f32", "f16" or "bf16" wavefield storage
     adjoint  : reserve the adjoint workspace for runs up to ``nt_max`` steps
     variant, zchunk, graph_steps : kernel tiling / replay options
-    tune : time the candidate tile shapes at create and keep the fastest (cached per grid shape)
+    tune : time the candidate tile shapes at create and keep the fastest (cached per grid shape; default on,
+           False = the fixed rule)
     cpml_width, cpml_reflection, cpml_f0 : CPML absorbing layers (float32 forward; sponge_width must be 0)
     cache_hint : 1 = keep A^{n-1}, m, A^{n+1} cacheable (float32 grids that fit the last-level cache);
                  0 = nontemporal (tune also times the cacheable policy)
@@ -42,7 +43,7 @@ class Solver:
 
     def __init__(self, vel: torch.Tensor, h, dt: float, src=None, rec=None, sponge_width: int = 0,
                  sponge_alpha: float = 0.015, storage: str = "f32", adjoint: bool = False, nt_max: int = 0,
-                 ckpt_interval: int = 0, variant: int = 0, zchunk: int = 0, graph_steps: int = 0, tune: bool = False,
+                 ckpt_interval: int = 0, variant: int = 0, zchunk: int = 0, graph_steps: int = 0, tune: bool = True,
                  cpml_width: int = 0, cpml_reflection: float = 1e-3, cpml_f0: float = 0.0, cache_hint: int = 0,
                  stream=None):
         lib = L.lib()
@@ -183,6 +184,13 @@ class Solver:
         n = ctypes.c_int32()
         L.check(L.lib().wave_time_index(self._h, ctypes.byref(n)), "wave_time_index")
         return n.value
+
+    def tiling(self) -> dict:
+        """The forward configuration in use: variant, zchunk, cache_hint (pass
+        them back to the constructor to reproduce a tuned choice)."""
+        out = (ctypes.c_int32 * 3)()
+        L.check(L.lib().wave_tiling(self._h, out), "wave_tiling")
+        return {"variant": int(out[0]), "zchunk": int(out[1]), "cache_hint": int(out[2])}
 
     def sync_status(self) -> int:
         f = ctypes.c_uint32()

@@ -140,14 +140,40 @@ def test_tiling_variants_and_zchunks_are_bitwise_identical():
                 assert np.array_equal(got["u"], base["u"]) and np.array_equal(got["traces"], base["traces"]), v
 
 
+def test_tiling_query_reproduces_the_tuned_choice():
+    """wave_tiling reports the configuration create settled on; passing it back
+    explicitly gives the same configuration and the same bits."""
+    from paper_2404_04441_amd import Solver
+
+    shape, h, vel, dt, nt, wav, rec, src, _ = ragged_case("box")
+    for nx in (71, 68):
+        v = torch.from_numpy(np.ascontiguousarray(vel[:, :, :nx], dtype=np.float32)).cuda()
+        r = rec[rec[:, 0] < nx]
+        w = torch.from_numpy(np.ascontiguousarray(wav, dtype=np.float32)).cuda()
+        outs, tilings = [], []
+        for kw in ({"tune": True}, None):
+            if kw is None:
+                kw = dict(tilings[0])
+            _say(f"case: tiling query nx={nx} {kw}")
+            s = Solver(v, h, dt, src=src, rec=r, sponge_width=5, sponge_alpha=0.05, **kw)
+            tilings.append(s.tiling())
+            tr = s.run(nt, w)
+            outs.append((s.read_field(0).cpu().numpy(), tr.cpu().numpy()))
+            s.close()
+        assert tilings[0] == tilings[1], tilings
+        assert 1 <= tilings[0]["variant"] and tilings[0]["zchunk"] >= 1
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_tuned_shape_is_bitwise_identical():
-    """Create-time tuning only chooses among shapes that compute the same bits."""
+    """Create-time tuning (the default) only chooses among shapes that compute
+    the same bits as the fixed rule."""
     shape, h, vel, dt, nt, wav, rec, src, _ = ragged_case("box")
     for nx in (71, 68):
         v = np.ascontiguousarray(vel[:, :, :nx])
         r = rec[rec[:, 0] < nx]
         _say(f"case: tune=True nx={nx}")
-        base = gpu_run(v, h, dt, src, wav, r, nt, sponge_width=5, sponge_alpha=0.05)
+        base = gpu_run(v, h, dt, src, wav, r, nt, sponge_width=5, sponge_alpha=0.05, tune=False)
         got = gpu_run(v, h, dt, src, wav, r, nt, sponge_width=5, sponge_alpha=0.05, tune=True)
         assert np.array_equal(got["u"], base["u"]) and np.array_equal(got["traces"], base["traces"])
         _say(f"case: tune=True cache_hint=1 nx={nx}")

@@ -89,7 +89,7 @@ typedef struct {
                                 workgroup's buffers span < 2 GiB; 0 = chosen from the grid size */
   int32_t graph_steps;       /* >0: replay steps from a captured HIP graph of this many steps */
   int32_t tune;              /* 1 (the default) with variant = 0 and zchunk = 0: wave_create times the candidate
-                                2.5D shapes and z-chunks (float32: both cache policies; float32
+                                2.5D shapes and z-chunks (without CPML: both cache policies; float32
                                 forward without CPML or adjoint: also the 3D-blocked gmem and
                                 smem shapes) for a few steps on the fresh (zero) fields and
                                 keeps the fastest; the choice is cached per (nx, ny, nz, storage,
@@ -108,12 +108,12 @@ typedef struct {
   double cpml_reflection;    /* CPML target reflection coefficient R in (0, 1] (default 1e-3):
                                 d(xi) = -3 v_max ln(R) xi^2 / (2 W h) */
   double cpml_f0;            /* CPML frequency shift alpha(xi) = pi f0 (1 - xi), Hz (default 0) */
-  int32_t cache_hint;        /* cache policy of the fields the float32 step reads or writes once
-                                (A^{n-1}, m, A^{n+1}): 0 = nontemporal, so that the cache keeps
-                                A^n's halo planes (with tune = 1 the regular policy is timed too);
-                                1 = regular, for grids whose fields fit the 256 MB last-level
-                                cache.  1 needs float32 storage, no CPML and a 2.5D variant.
-                                Results are the same bits either way */
+  int32_t cache_hint;        /* cache policy of the fields the forward step reads or writes once
+                                (float32: A^{n-1}, m, A^{n+1}; 16-bit: V^n, m, A^{n+1}, V^{n+1}):
+                                0 = nontemporal, so that the cache keeps A^n's halo planes (with
+                                tune = 1 the regular policy is timed too); 1 = regular, for grids
+                                whose fields fit the 256 MB last-level cache.  1 needs no CPML
+                                and a 2.5D variant.  Results are the same bits either way */
 } wave_params;
 
 /* Fill `p` with defaults: no source, no receivers, float32 storage,

@@ -96,8 +96,8 @@ struct StepArgs {
   // it, the y and z parts by a pass after it)
   int cpml;
   CpmlArgs cp;
-  // 1: A^{n-1}, m and A^{n+1} with the regular cache policy (float32 forward
-  // 2.5D, no CPML), for grids whose fields fit the last-level cache
+  // 1: the fields read or written once with the regular cache policy
+  // (forward 2.5D, no CPML), for grids whose fields fit the last-level cache
   int keep;
 };
 

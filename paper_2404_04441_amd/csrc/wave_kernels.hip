@@ -270,10 +270,11 @@ static_assert(kPadZ >= (kQ - 1) + kMaxPD + R, "z padding must cover the last tri
 // lanes' values).  The y and z parts follow in cpml_fix_kernel over the rows
 // and planes within W + R of a y or z face: in the streaming kernel their
 // neighbours would be loads the z loop waits on in every such row and plane.
-// KEEP: A^{n-1}, m and A^{n+1} use the regular cache policy instead of the
+// KEEP: the fields read or written once (float32: A^{n-1}, m, A^{n+1};
+// 16-bit: V^n, m, A^{n+1}, V^{n+1}) use the regular cache policy instead of the
 // nontemporal one, so that a grid whose fields fit the last-level cache stays
-// there from step to step (float32 forward; chosen by create-time tuning or
-// the caller).
+// there from step to step (forward; chosen by create-time tuning or the
+// caller).
 template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ, bool CP, bool KEEP>
 __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   using C = Codec<S>;
@@ -291,7 +292,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   static_assert(VEC == 1 || VEC == 2 || VEC == 4, "lane width");
   static_assert(!(SEMI && ADJ), "the semi-stencil form is forward only");
   static_assert(!CP || (S == kF32 && !SEMI && !ADJ), "the fused CPML step is float32 forward");
-  static_assert(!KEEP || (S == kF32 && !SEMI && !ADJ && !CP), "the cached policy is for the plain float32 step");
+  static_assert(!KEEP || (!SEMI && !ADJ && !CP), "the cached policy is for the plain forward step");
   constexpr int NTP = KEEP ? 0 : kNT;  // cache policy of the fields read or written once
   // each LDS plane ends with a scratch row: halo writes of lanes or
   // wavefronts with nothing to write go there, so no write is predicated
@@ -799,8 +800,8 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
             sv[i] = vv[i] * sv_next;
           }
           const Words<NA> ra = row_put<S, VEC>(sa), rv = row_put<S, VEC>(sv);
-          st_words<NA, kNT>(ra, rO, vrow[j], sz0);
-          st_words<NA, kNT>(rv, rVo, vrow[j], sz0);
+          st_words<NA, NTP>(ra, rO, vrow[j], sz0);
+          st_words<NA, NTP>(rv, rVo, vrow[j], sz0);
 #pragma unroll
           for (int i = 0; i < VEC; ++i) {
             const float stored = row_get<S>(ra, i);
@@ -1538,7 +1539,7 @@ hipError_t launch_one(const StepArgs &a, hipStream_t s) {
         return hipGetLastError();
       }
     }
-    if constexpr (S == kF32 && !ADJ) {
+    if constexpr (!ADJ) {
       if (a.keep) {
         hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, false, false, true>), dim3(grid), dim3(64 * BY),
                            0, s, a);

@@ -82,10 +82,9 @@ int validate(const wave_params *p) {
   }
   if (p->zchunk < 0 || p->graph_steps < 0) return WAVE_EINVAL;
   if (p->tune < 0 || p->tune > 1) return WAVE_EINVAL;
-  // the cached policy exists for the float32 2.5D forward kernels without CPML
+  // the cached policy exists for the 2.5D forward kernels without CPML
   if (p->cache_hint < 0 || p->cache_hint > 1) return WAVE_EINVAL;
-  if (p->cache_hint == 1 &&
-      (p->storage != WAVE_F32 || p->cpml_width > 0 || (p->variant > 0 && variant_info(p->variant).family != 0)))
+  if (p->cache_hint == 1 && (p->cpml_width > 0 || (p->variant > 0 && variant_info(p->variant).family != 0)))
     return WAVE_EINVAL;
   return WAVE_OK;
 }
@@ -186,7 +185,7 @@ bool detect_box(const std::vector<int32_t> &rec, int nrec, RecBox *b) {
 // One tile decomposition of the grid for a step-kernel variant.
 struct Tiling {
   int variant = 0, tiles_x = 0, tiles_y = 0, nchunks = 0, zchunk = 0, total_tiles = 0;
-  bool keep = false;  // float32 forward: regular cache policy for the fields streamed once
+  bool keep = false;  // forward: regular cache policy for the fields streamed once
 };
 
 // Measured-best tile shapes on MI355X (variant indices of the kernel
@@ -477,9 +476,9 @@ int tune_forward(wave_ctx *w) {
       if (zc < p.nz && t.zchunk != cands.back().zchunk) cands.push_back(t);
     }
   }
-  // float32 without CPML: every candidate also with the cached policy
+  // without CPML: every 2.5D candidate also with the cached policy
   // (cache_hint 0), or only with it (cache_hint 1)
-  if (p.storage == WAVE_F32 && !w->cpml) {
+  if (!w->cpml) {
     const size_t n = cands.size();
     for (size_t i = 0; i < n; ++i) {
       if (variant_info(cands[i].variant).family != 0) continue;

@@ -37,8 +37,8 @@ class Solver:
     tune : time the candidate tile shapes at create and keep the fastest (cached per grid shape; default on,
            False = the fixed rule)
     cpml_width, cpml_reflection, cpml_f0 : CPML absorbing layers (float32 forward; sponge_width must be 0)
-    cache_hint : 1 = keep A^{n-1}, m, A^{n+1} cacheable (float32 grids that fit the last-level cache);
-                 0 = nontemporal (tune also times the cacheable policy)
+    cache_hint : 1 = keep the fields read or written once cacheable (grids that fit the last-level
+                 cache); 0 = nontemporal (tune also times the cacheable policy)
     """
 
     def __init__(self, vel: torch.Tensor, h, dt: float, src=None, rec=None, sponge_width: int = 0,

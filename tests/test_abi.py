@@ -101,6 +101,7 @@ def test_cache_hint_accepted(lib):
     assert _bytes(lib, _params(lib, cache_hint=1))[0] == 0
     assert _bytes(lib, _params(lib, cache_hint=1, variant=12, nx=16))[0] == 0
     assert _bytes(lib, _params(lib, cache_hint=1, adjoint=1, nt_max=10))[0] == 0
+    assert _bytes(lib, _params(lib, cache_hint=1, storage=L.WAVE_F16))[0] == 0
 
 
 def test_plane_size_limit(lib):
@@ -117,7 +118,7 @@ def test_plane_size_limit(lib):
     dict(cpml_width=-1), dict(cpml_width=3, sponge_width=2), dict(cpml_width=3, storage=L.WAVE_F16),
     dict(cpml_width=3, adjoint=1, nt_max=10), dict(cpml_width=6), dict(cpml_width=3, cpml_reflection=0.0),
     dict(cpml_width=3, cpml_reflection=1.5), dict(cpml_width=3, cpml_f0=-1.0),
-    dict(cache_hint=2), dict(cache_hint=-1), dict(cache_hint=1, storage=L.WAVE_F16),
+    dict(cache_hint=2), dict(cache_hint=-1),
     dict(cache_hint=1, cpml_width=3), dict(cache_hint=1, variant=14),
 ])
 def test_invalid_params_rejected(lib, kw):

@@ -183,3 +183,7 @@ def test_storage_tile_variants_bitwise_identical():
                     continue
                 assert not refuse, v
                 assert np.array_equal(got["u"], base["u"]) and np.array_equal(got["traces"], base["traces"])
+                if v % 4 == 1:  # some shapes also with the cached policy: same bits
+                    got = gpu_run(vc, h, dt, src, wav, rc, nt, sponge_width=5, sponge_alpha=0.05, storage=fmt,
+                                  variant=v, zchunk=11, cache_hint=1)
+                    assert np.array_equal(got["u"], base["u"]) and np.array_equal(got["traces"], base["traces"])

@@ -39,15 +39,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage: str):
+def measured_traffic(storage: str, tiling: dict):
     """HBM bytes per step kernel from committed rocprofv3 counter runs, only
-    if they were taken on the current kernel source."""
+    if they were taken on the current kernel source and the same step
+    configuration (variant, z-chunk, cache policy)."""
     path = os.path.join(ROOT, "profiles", f"traffic_step_large_{storage}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_sha") != kernel_source_hash():
+    if rec.get("kernel_sha") != kernel_source_hash() or rec.get("tiling") != tiling:
         return None
     return rec.get("bytes_per_launch")
 
@@ -324,9 +325,10 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
-    ap.add_argument("--no-tune", action="store_true",
-                    help="the fixed tile-shape rule instead of create-time tuning (shape, z-chunk, cache policy; "
-                         "outside the timed region)")
+    ap.add_argument("--tune", action="store_true",
+                    help="create-time tuning (shape, z-chunk, cache policy; outside the timed region) instead of "
+                         "the fixed rule, whose 512^3 choice tuning also finds; the fixed rule keeps counter runs "
+                         "on one kernel configuration")
     ap.add_argument("--nt", type=int, default=0, help="time steps per shot (default: the workload's 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
@@ -368,7 +370,7 @@ def main():
     wav = torch.from_numpy(W.wavelet(nt)).to(dev)
     s = Solver(torch.from_numpy(vel).to(dev), W.h, W.dt, src=W.src, rec=W.rec, sponge_width=W.sponge_width,
                sponge_alpha=W.sponge_alpha, storage=args.storage, variant=args.variant, zchunk=args.zchunk,
-               tune=not args.no_tune)
+               tune=args.tune)
     traces = torch.empty((nt, len(W.rec)), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
@@ -400,6 +402,7 @@ def main():
     bpp = BYTES_PER_POINT[args.storage]
     achieved = bpp * W.npts / (kernel_ms * 1e-3) / 1e9
     flags = s.sync_status()
+    tiling = s.tiling()
     s.close()
 
     if args.copy_calibration:
@@ -431,9 +434,9 @@ def main():
         "config": {"workload": f"{W.name} FP32 fused forward shot: 8th-order star stencil, leapfrog, "
                                f"20-node sponge, Ricker source at (256,256,10), 512x512 receiver plane z=0",
                    "grid": list(W.shape[::-1]), "time_steps": nt, "storage": args.storage,
-                   "variant": args.variant, "zchunk": args.zchunk, "tuned": not args.no_tune},
+                   "variant": args.variant, "zchunk": args.zchunk, "tuned": bool(args.tune), "tiling": tiling},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.storage),
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.storage, tiling),
                      "kernel": "step_kernel", "kernel_ms": round(kernel_ms, 4),
                      "algorithmic_bytes_per_launch": bpp * W.npts},
         "nonfinite": bool(flags),

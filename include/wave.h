@@ -92,7 +92,8 @@ typedef struct {
                                 2.5D shapes and z-chunks (without CPML: both cache policies; float32
                                 forward without CPML or adjoint: also the 3D-blocked gmem and
                                 smem shapes) for a few steps on the fresh (zero) fields and
-                                keeps the fastest; the choice is cached per (nx, ny, nz, storage,
+                                keeps the fastest (the fixed rule's choice unless another is more
+                                than 3% faster); the choice is cached per (nx, ny, nz, storage,
                                 CPML or not, cache_hint) for the life of the process.  Every
                                 choice computes the same bits; wave_tiling reports it.  0: the
                                 fixed automatic rule (measured: 30-50% slower at some sizes) */

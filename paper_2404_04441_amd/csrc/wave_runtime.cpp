@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "wave.h"
@@ -454,10 +455,34 @@ int tune_forward(wave_ctx *w) {
         return WAVE_OK;
       }
   }
-  std::vector<Tiling> cands;
-  // the 3D-blocked families compute the same bits as the 2.5D shapes (float32
-  // forward); on small grids, where everything stays in cache, they can win
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = hip_rc(hipEventCreate(&e0));
+  if (!rc) rc = hip_rc(hipEventCreate(&e1));
+  // no source while timing (the wavelet is not known yet); the fields stay zero
+  const int src_x = w->p.src[0];
+  w->p.src[0] = -1;
+  const Tiling fixed = w->fwd;
+  // milliseconds of 3 steps after 1 warm-up step, or a negative value on error
+  auto time_one = [&](const Tiling &t) {
+    w->fwd = t;
+    w->cpml_fused = w->cpml && variant_fuses_cpml(t.variant);
+    int r = enqueue_steps(w, 1, nullptr, nullptr, false);
+    if (!r) r = hip_rc(hipEventRecord(e0, w->stream));
+    if (!r) r = enqueue_steps(w, 3, nullptr, nullptr, false);
+    if (!r) r = hip_rc(hipEventRecord(e1, w->stream));
+    if (!r) r = hip_rc(hipEventSynchronize(e1));
+    float ms = 0.f;
+    if (!r) r = hip_rc(hipEventElapsedTime(&ms, e0, e1));
+    if (r) rc = r;
+    return r ? -1.f : ms;
+  };
+  // stage 1: the fixed rule's choice, then every shape at its automatic
+  // z-chunk, 2.5D shapes with both cache policies where they apply (only the
+  // cached one for cache_hint 1).  The 3D-blocked families compute the same
+  // bits as the 2.5D shapes (float32 forward); on small grids, where
+  // everything stays in cache, they can win.
   const bool blocked_ok = p.storage == WAVE_F32 && !w->cpml && !p.adjoint && p.cache_hint == 0;
+  std::vector<Tiling> cands{fixed};
   for (int v = 1; v < variant_count(); ++v) {
     const Variant info = variant_info(v);
     if ((info.family == 1 || info.family == 2) && blocked_ok) {
@@ -469,49 +494,45 @@ int tune_forward(wave_ctx *w) {
     wave_params q = p;
     q.variant = v;
     q.zchunk = 0;
-    cands.push_back(make_tiling(&q, v));
-    for (int zc : {27, 45, 72, 99, 135, 198, 270}) {
-      q.zchunk = zc;
-      const Tiling t = make_tiling(&q, v);
-      if (zc < p.nz && t.zchunk != cands.back().zchunk) cands.push_back(t);
-    }
-  }
-  // without CPML: every 2.5D candidate also with the cached policy
-  // (cache_hint 0), or only with it (cache_hint 1)
-  if (!w->cpml) {
-    const size_t n = cands.size();
-    for (size_t i = 0; i < n; ++i) {
-      if (variant_info(cands[i].variant).family != 0) continue;
-      Tiling t = cands[i];
+    Tiling t = make_tiling(&q, v);
+    t.keep = p.cache_hint == 1;
+    cands.push_back(t);
+    if (!w->cpml && p.cache_hint == 0) {
       t.keep = true;
-      if (p.cache_hint == 1)
-        cands[i] = t;
-      else
-        cands.push_back(t);
+      cands.push_back(t);
     }
   }
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  int rc = hip_rc(hipEventCreate(&e0));
-  if (!rc) rc = hip_rc(hipEventCreate(&e1));
-  // no source while timing (the wavelet is not known yet); the fields stay zero
-  const int src_x = w->p.src[0];
-  w->p.src[0] = -1;
-  Tiling best = w->fwd;
-  float best_ms = 3.0e38f;
-  for (size_t i = 0; i < cands.size() && !rc; ++i) {
-    w->fwd = cands[i];
-    w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
-    rc = enqueue_steps(w, 1, nullptr, nullptr, false);
-    if (!rc) rc = hip_rc(hipEventRecord(e0, w->stream));
-    if (!rc) rc = enqueue_steps(w, 3, nullptr, nullptr, false);
-    if (!rc) rc = hip_rc(hipEventRecord(e1, w->stream));
-    if (!rc) rc = hip_rc(hipEventSynchronize(e1));
-    float ms = 0.f;
-    if (!rc) rc = hip_rc(hipEventElapsedTime(&ms, e0, e1));
-    if (!rc && ms < best_ms) {
-      best_ms = ms;
-      best = cands[i];
+  std::vector<std::pair<float, Tiling>> timed;
+  for (size_t i = 0; i < cands.size() && !rc; ++i) timed.emplace_back(time_one(cands[i]), cands[i]);
+  // stage 2: the z-chunk list for the four fastest 2.5D candidates of stage 1
+  std::vector<std::pair<float, Tiling>> top;
+  for (const auto &c : timed)
+    if (variant_info(c.second.variant).family == 0) top.push_back(c);
+  std::sort(top.begin(), top.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+  if (top.size() > 4) top.resize(4);
+  for (const auto &c : top) {
+    wave_params q = p;
+    q.variant = c.second.variant;
+    for (int zc : {27, 45, 72, 99, 135, 198, 270}) {
+      if (rc || zc >= p.nz) break;
+      q.zchunk = zc;
+      Tiling t = make_tiling(&q, q.variant);
+      t.keep = c.second.keep;
+      if (t.zchunk != c.second.zchunk) timed.emplace_back(time_one(t), t);
     }
+  }
+  // the fixed rule's choice (timed first) stays unless another candidate is
+  // more than 3% faster, so near-ties (timing noise) do not move the choice
+  Tiling best = fixed;
+  if (!rc) {
+    const float base_ms = timed.front().first;
+    float best_ms = base_ms;
+    for (const auto &c : timed)
+      if (c.first < best_ms) {
+        best_ms = c.first;
+        best = c.second;
+      }
+    if (best_ms > 0.97f * base_ms) best = fixed;
   }
   w->p.src[0] = src_x;
   w->fwd = best;

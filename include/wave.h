@@ -88,10 +88,11 @@ typedef struct {
   int32_t zchunk;            /* z-planes per workgroup, rounded up to a multiple of 9 and capped so a
                                 workgroup's buffers span < 2 GiB; 0 = chosen from the grid size */
   int32_t graph_steps;       /* >0: replay steps from a captured HIP graph of this many steps */
-  int32_t tune;              /* 1 (the default) with variant = 0 and zchunk = 0: wave_create times the candidate
-                                2.5D shapes and z-chunks (without CPML: both cache policies; float32
-                                forward without CPML or adjoint: also the 3D-blocked gmem and
-                                smem shapes) for a few steps on the fresh (zero) fields and
+  int32_t tune;              /* 1 (the default) with variant = 0 and zchunk = 0: wave_create
+                                times candidate configurations for a few steps on the fresh
+                                (zero) fields: the 2.5D shapes and z-chunks, both cache policies
+                                (without CPML or adjoint), and for float32 forward runs without
+                                CPML or adjoint also the 3D-blocked gmem and smem shapes.  It
                                 keeps the fastest (the fixed rule's choice unless another is more
                                 than 3% faster); the choice is cached per (nx, ny, nz, storage,
                                 CPML or not, cache_hint) for the life of the process.  Every

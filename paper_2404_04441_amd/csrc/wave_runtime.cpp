@@ -478,7 +478,8 @@ int tune_forward(wave_ctx *w) {
   };
   // stage 1: the fixed rule's choice, then every shape at its automatic
   // z-chunk, 2.5D shapes with both cache policies where they apply (only the
-  // cached one for cache_hint 1).  The 3D-blocked families compute the same
+  // cached one for cache_hint 1; not for adjoint contexts, whose recomputation
+  // streams the checkpoint buffer through the same cache).  The 3D-blocked families compute the same
   // bits as the 2.5D shapes (float32 forward); on small grids, where
   // everything stays in cache, they can win.
   const bool blocked_ok = p.storage == WAVE_F32 && !w->cpml && !p.adjoint && p.cache_hint == 0;
@@ -497,7 +498,7 @@ int tune_forward(wave_ctx *w) {
     Tiling t = make_tiling(&q, v);
     t.keep = p.cache_hint == 1;
     cands.push_back(t);
-    if (!w->cpml && p.cache_hint == 0) {
+    if (!w->cpml && p.cache_hint == 0 && !p.adjoint) {
       t.keep = true;
       cands.push_back(t);
     }

@@ -76,7 +76,8 @@ def test_gradient_matches_oracle_adjoint(rec_kind, W):
 
 def test_checkpoint_interval_and_variant_invariance():
     """Recomputation from checkpoints is deterministic: any interval, from
-    one segment (store all) to a checkpoint every step, gives the same bits."""
+    one segment (store all) to a checkpoint every step, any tile shape and
+    either cache policy give the same bits."""
     c = case("box", 4)
     base = gpu_grad(c)
     for K in (1, 7, 12, 150):
@@ -85,6 +86,10 @@ def test_checkpoint_interval_and_variant_invariance():
     for v in (1, 2, 3):
         _say(f"case: variant={v}")
         assert np.array_equal(gpu_grad(c, variant=v), base), v
+    _say("case: cache_hint=1 (forward and recomputation with the cached policy)")
+    assert np.array_equal(gpu_grad(c, cache_hint=1), base)
+    _say("case: tune=False (the fixed rule's forward shape)")
+    assert np.array_equal(gpu_grad(c, tune=False), base)
 
 
 def test_gradient_central_differences_float32():

@@ -4,7 +4,7 @@ The runtime source is compiled with g++ and the sanitizers (host code only),
 linked with the normally built kernel object into a small C driver
 (tests/abi_sanitize_driver.c) that exercises every path reachable without a
 GPU.  Any out-of-bounds access, use-after-free or undefined behaviour aborts
-the driver."""
+that program."""
 import os
 import shutil
 import subprocess

@@ -95,7 +95,7 @@ typedef struct {
                                 CPML or adjoint also the 3D-blocked gmem and smem shapes.  It
                                 keeps the fastest (the fixed rule's choice unless another is more
                                 than 3% faster); the choice is cached per (nx, ny, nz, storage,
-                                CPML or not, cache_hint) for the life of the process.  Every
+                                CPML, adjoint, cache_hint) for the life of the process.  Every
                                 choice computes the same bits; wave_tiling reports it.  0: the
                                 fixed automatic rule (measured: 30-50% slower at some sizes) */
   int32_t cpml_width;        /* >0: CPML absorbing layers of this many nodes on all six faces (the

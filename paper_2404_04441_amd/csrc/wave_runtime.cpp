@@ -437,7 +437,7 @@ int do_reset(wave_ctx *w) {
 // identical bits, so the choice only changes speed.
 struct TuneEntry {
   int nx, ny, nz, storage, cache_hint;
-  bool cpml;
+  bool cpml, adjoint;
   Tiling t;
 };
 std::mutex g_tune_mu;
@@ -449,7 +449,7 @@ int tune_forward(wave_ctx *w) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     for (const TuneEntry &e : g_tune_cache)
       if (e.nx == p.nx && e.ny == p.ny && e.nz == p.nz && e.storage == p.storage && e.cpml == w->cpml &&
-          e.cache_hint == p.cache_hint) {
+          e.cache_hint == p.cache_hint && e.adjoint == (p.adjoint != 0)) {
         w->fwd = e.t;
         w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
         return WAVE_OK;
@@ -542,7 +542,7 @@ int tune_forward(wave_ctx *w) {
   if (e1) (void)hipEventDestroy(e1);
   if (!rc) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune_cache.push_back(TuneEntry{p.nx, p.ny, p.nz, p.storage, p.cache_hint, w->cpml, best});
+    g_tune_cache.push_back(TuneEntry{p.nx, p.ny, p.nz, p.storage, p.cache_hint, w->cpml, p.adjoint != 0, best});
   }
   return rc;
 }

@@ -135,8 +135,10 @@ int wave_workspace_bytes(const wave_params *p, size_t *bytes);
  * during the call only (m is stored in the workspace).  ws_dev: device
  * workspace of ws_bytes >= wave_workspace_bytes, 256-byte aligned, owned by
  * the caller and borrowed until wave_destroy.  hip_stream: the hipStream_t all
- * work is queued on (NULL = default stream).  Synchronises that stream once to
- * read back the velocity range.  Errors: WAVE_EINVAL (bad params, pointer,
+ * work is queued on (NULL = default stream).  Synchronises that stream to read
+ * back the velocity range and, with tune = 1 (a grid shape not yet tuned in
+ * this process), to time a few steps of each candidate configuration on the
+ * zeroed fields.  Errors: WAVE_EINVAL (bad params, pointer,
  * alignment, non-finite or non-positive velocity), WAVE_ENOSPC (workspace too
  * small), WAVE_EUNSTABLE (max(v) dt above the leapfrog stability limit
  * 2 / sqrt(2048/315 * sum_a h_a^-2)), WAVE_EHIP.  The state is reset:
@@ -227,8 +229,11 @@ int wave_variant_count(void);
  * Families 1 and 2 are the paper's 3D-blocking designs of the same section
  * ("gmem": every stencil value from global memory; "smem": a 3D tile with
  * its halo staged in shared memory): blocks of 64 x by x ry nodes, float32
- * storage and forward steps only.  Errors: WAVE_EINVAL for a null `info` or
- * an out-of-range variant. */
+ * storage and forward steps only; they compute the same bits as family 0.
+ * Family 3 is the 2.5D blocking with the z sum as a semi-stencil (the
+ * paper's st_semi, same section): float32 forward only, the z sum in another
+ * order (not bitwise equal to family 0).  Errors: WAVE_EINVAL for a null
+ * `info` or an out-of-range variant. */
 int wave_variant_info(int32_t variant, int32_t *info);
 
 /* Static text for a status code. */

@@ -8,6 +8,8 @@ for shapes without a fused kernel, the plain step and a correction pass for
 all three) must match it within the float32 tolerance of the plain step, on
 ragged grids with receivers inside and outside the layers.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -131,3 +133,56 @@ def test_cpml_layer_as_thick_as_half_the_grid():
     e_u = oracle.rel_l2(got["u"], ref["u"])
     _say(f"case: W = nz/2: rel-L2 field {e_u:.3e}")
     assert e_u <= TOL
+
+
+@functools.lru_cache(maxsize=None)
+def _large_velocity():
+    from synth import workload
+
+    return workload("large").velocity()
+
+
+@pytest.mark.parametrize("corner", ["low", "high"])
+def test_cpml_full_size_light_cone(corner):
+    """The 512^3 CPML configuration the bench times (W = 20, R = 1e-3,
+    f0 = 15 Hz, the same create-time choice of fused shape), with the source
+    inside a corner's layers, checked against the oracle at full size.
+
+    In the layers a step reaches at most 8 nodes along an axis (D1 of psi,
+    which is D1 of A), so after k = 6 steps the field is zero beyond 48 nodes
+    of the source.  The oracle runs on the 96^3 cube at that corner (profiles
+    from the full grid's v_max; the cube's inner faces and their layers lie
+    beyond the reach), which gives the exact reference inside the cube; every
+    node outside the cube must be exactly zero on the GPU."""
+    from paper_2404_04441_amd import Solver
+    from synth import workload
+
+    W = workload("large")
+    vel = _large_velocity()
+    nz, ny, nx = vel.shape
+    k, C = 6, 96
+    if corner == "low":
+        src = (6, 7, 5)
+        sl = (slice(0, C),) * 3
+        src_c = src
+    else:
+        src = (nx - 7, ny - 6, nz - 8)
+        sl = (slice(nz - C, nz), slice(ny - C, ny), slice(nx - C, nx))
+        src_c = (src[0] - (nx - C), src[1] - (ny - C), src[2] - (nz - C))
+    wav = W.wavelet(k)
+    _say(f"case: CPML 512^3 light cone, {corner} corner, source {src}, {k} steps")
+    s = Solver(torch.from_numpy(vel).cuda(), W.h, W.dt, src=src, rec=None, cpml_width=W.sponge_width, cpml_f0=W.f0)
+    s.run(k, torch.from_numpy(wav).cuda())
+    u = s.read_field(0)
+    crop = u[sl].cpu().numpy()
+    u[sl] = 0
+    outside = float(u.abs().max())
+    torch.cuda.synchronize()
+    s.close()
+    ref = forward_cpml(np.ascontiguousarray(vel[sl]), W.h, W.dt, src_c, wav, np.zeros((0, 3), dtype=np.int32), k,
+                       width=W.sponge_width, f0=W.f0, vmax=float(vel.max()))
+    assert np.abs(ref["psi"][0]).max() > 0 and np.abs(ref["zeta"][2]).max() > 0  # the layers are active
+    e = oracle.rel_l2(crop, ref["u"])
+    _say(f"rel-L2 in the corner cube {e:.3e}, max outside {outside:.1e}")
+    assert outside == 0.0
+    assert e <= TOL

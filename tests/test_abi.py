@@ -160,6 +160,15 @@ def test_null_context_calls(lib):
     assert lib.wave_sync_status(None, ctypes.byref(f)) == L.WAVE_EINVAL
     assert lib.wave_destroy(None) == L.WAVE_EINVAL
     assert lib.wave_workspace_bytes(None, None) == L.WAVE_EINVAL
+    out = (ctypes.c_int32 * 3)()
+    assert lib.wave_tiling(None, out) == L.WAVE_EINVAL
+
+
+def test_params_defaults(lib):
+    p = L.WaveParams()
+    lib.wave_params_init(ctypes.byref(p))
+    assert p.tune == 1 and p.cache_hint == 0 and p.variant == 0 and p.zchunk == 0
+    assert p.storage == L.WAVE_F32 and p.src[0] < 0 and p.cpml_width == 0
 
 
 def test_status_strings_and_variants(lib):

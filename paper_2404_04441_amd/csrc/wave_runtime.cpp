@@ -514,7 +514,7 @@ int tune_forward(wave_ctx *w) {
   for (const auto &c : top) {
     wave_params q = p;
     q.variant = c.second.variant;
-    for (int zc : {27, 45, 72, 99, 135, 198, 270}) {
+    for (int zc : {9, 18, 27, 45, 72, 99, 135, 198, 270}) {
       if (rc || zc >= p.nz) break;
       q.zchunk = zc;
       Tiling t = make_tiling(&q, q.variant);

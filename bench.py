@@ -104,6 +104,22 @@ def stream_ceiling(dev, n: int) -> dict:
     return out
 
 
+def copy_calibration(dev) -> None:
+    """A plain device copy of known size (2 GiB read, 2 GiB written, three
+    times): its FETCH_SIZE / WRITE_SIZE counters give the factor between
+    counter readings and bytes moved."""
+    import torch
+
+    src = torch.ones(1 << 29, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: 3 x {src.numel() * 4} bytes read and written", file=sys.stderr, flush=True)
+    del src, dst
+    torch.cuda.empty_cache()
+
+
 def kernel_rate(s, nt, wav, traces, npts, bpp):
     """Average step-kernel time (events on the solver's stream) -> Gpts/s, GB/s."""
     import torch
@@ -371,6 +387,8 @@ def main():
     dev = torch.device("cuda:0")
     W = workload("large")
     if args.cpml_only:
+        if args.copy_calibration:
+            copy_calibration(dev)
         v_dev = torch.from_numpy(W.velocity()).to(dev)
         print(json.dumps({"cpml_512": cpml_leg(W, v_dev, min(args.nt or W.nt, 200))}), flush=True)
         return
@@ -416,16 +434,7 @@ def main():
     s.close()
 
     if args.copy_calibration:
-        # a plain copy of known size: its FETCH_SIZE/WRITE_SIZE counters give
-        # the factor between counter readings and bytes moved
-        src = torch.ones(1 << 29, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"[bench] copy calibration: 3 x {src.numel() * 4} bytes read and written", file=sys.stderr,
-              flush=True)
-        del src, dst
+        copy_calibration(dev)
     ceiling = stream_ceiling(dev, W.npts)
 
     out = {

@@ -23,14 +23,17 @@
 //  * loads run PD planes ahead of the plane being computed (a register
 //    pipeline), so enough bytes are in flight to cover HBM latency;
 //  * A^{n-1}, m and A^{n+1} are touched exactly once: they use nontemporal
-//    loads/stores so that L2 keeps the A^n planes the neighbours' halos need;
+//    loads/stores so that L2 keeps the A^n planes the neighbours' halos need
+//    (the KEEP instances use the regular policy instead, for grids whose
+//    fields fit the last-level cache);
 //  * workgroup ids are remapped so that each XCD (hardware dispatches ids
 //    round-robin over the 8 XCDs) owns a contiguous run of tiles, keeping
 //    halo re-reads inside one XCD's L2.
 //
 // Beside it: the paper's 3D-blocked designs (gmem, smem) and a semi-stencil
-// form for the kernel study, the CPML boundary kernels, and small utility
-// kernels (setup, decode, gather/scatter, gradient, fills).
+// form for the kernel study, the CPML boundary (its x part fused into the
+// step kernel, the memory-variable update and the y/z part in row kernels),
+// and small utility kernels (setup, decode, gather/scatter, gradient, fills).
 #include <hip/hip_runtime.h>
 
 #include <utility>

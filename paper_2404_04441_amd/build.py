@@ -6,6 +6,7 @@ from __future__ import annotations
 
 import os
 import shutil
+from concurrent.futures import ThreadPoolExecutor
 import subprocess
 import sys
 
@@ -16,7 +17,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwave.so")
 ARCH = "gfx950"
 
-SOURCES = ["wave_kernels.hip", "wave_runtime.cpp"]
+# The step-kernel templates (step_kernels.h) are instantiated in one unit per
+# storage type and one for the adjoint, so the units compile in parallel.
+SOURCES = ["step_f32.hip", "step_f16.hip", "step_bf16.hip", "step_adj.hip", "wave_kernels.hip", "wave_runtime.cpp"]
 
 # Packed-FP32 instructions stay off: they are not used on purpose anywhere in
 # the kernels, and the compiler would otherwise form them from float pairs.
@@ -33,7 +36,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source for gfx950 and link libwave.so; returns its path."""
     cc = hipcc()
-    objs = []
+    objs, cmds = [], []
     build_dir = os.path.join(PKG, "_build")
     os.makedirs(build_dir, exist_ok=True)
     for src in SOURCES:
@@ -43,8 +46,12 @@ def build(verbose: bool = False) -> str:
         if src.endswith(".hip"):
             cmd[1:1] = ["-x", "hip"]
             cmd += DEVICE_FLAGS
-        _run(cmd, verbose)
+        cmds.append(cmd)
         objs.append(obj)
+    jobs = max(1, min(len(cmds), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(jobs) as pool:
+        for f in [pool.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)

@@ -28,8 +28,11 @@ What each module follows:
   (the paper is silent on precision; parity unpinned, see module header).
 * ``cpml`` -- the CPML absorbing boundary (the paper's boundary, cited in
   Sec. II / IV-A without formulas; the formulation is a reading, see its
-  header), pinned by textbook weights, the undamped limit and absorption
-  against a large-domain reference.
+  header), pinned by textbook weights, the closed-form harmonic steady
+  state of its memory recursion (update order), the continuous PML's
+  reflection coefficient and memory kernel (profile and recursion
+  coefficients), the undamped limit and absorption against a large-domain
+  reference.
 """
 from .coefficients import fd_coefficients, second_derivative_weights
 from .operators import laplacian, sponge_profile, sponge_field, stability_courant, symbol_peak

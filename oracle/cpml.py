@@ -95,6 +95,20 @@ def d2(u, axis, h):
     return acc / (h * h)
 
 
+def memory_update(p, psi, zeta, a, b, axis, h):
+    """One time level of the memory variables of one axis, in the order the
+    two applications of the stretch require: psi^n from p^n first, then zeta^n
+    from D2 p^n and the derivative of that new psi^n.
+
+    Returns (psi^n, zeta^n, stretched second derivative D2 p^n + D1 psi^n +
+    zeta^n).  Works for complex p (harmonic forcing in the tests)."""
+    psi_new = b * psi + a * d1(p, axis, h)
+    second = d2(p, axis, h)
+    dpsi = d1(psi_new, axis, h)
+    zeta_new = b * zeta + a * (second + dpsi)
+    return psi_new, zeta_new, second + dpsi + zeta_new
+
+
 def forward_cpml(vel, h, dt, src, wavelet, rec, nt, width, f0, reflection=1e-3, vmax=None, dtype=np.float64,
                  snapshots=()):
     """``nt`` leapfrog steps with CPML layers of ``width`` nodes on all six faces.
@@ -126,11 +140,8 @@ def forward_cpml(vel, h, dt, src, wavelet, rec, nt, width, f0, reflection=1e-3, 
         total = np.zeros(v.shape, dtype=dtype)
         for k, (axis, ha, _) in enumerate(axes):
             a, b = ab[k]
-            psi[k] = b * psi[k] + a * d1(cur, axis, ha)
-            second = d2(cur, axis, ha)
-            dpsi = d1(psi[k], axis, ha)
-            zeta[k] = b * zeta[k] + a * (second + dpsi)
-            total = total + second + dpsi + zeta[k]
+            psi[k], zeta[k], term = memory_update(cur, psi[k], zeta[k], a, b, axis, ha)
+            total = total + term
         new = 2 * cur - prev + dt * dt * v * v * total
         if src is not None:
             ix, iy, iz = src

@@ -2,8 +2,8 @@
  * libwave -- 3D constant-density acoustic wave propagation on one gfx950 GPU.
  *
  * The operation (paper Sec. II, Eq. 1): the 25-point, 8th-order (radius 4)
- * star Laplacian L, applied at every grid node once per time iteration to
- * update the wavefield.  The time integrator (not named in the paper) is the
+ * star Laplacian L, evaluated at every grid node in each time step to advance
+ * the wavefield.  The time integrator (not named in the paper) is the
  * 2nd-order leapfrog; an exponential sponge (Cerjan) damps the outer
  * `sponge_width` nodes; a point source injects a wavelet; receivers sample
  * the field.  One step, fused into one kernel pass over the grid:
@@ -182,6 +182,14 @@ int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *re
  * which = 0: A^n; which = 1: A^{n-1} (undamped); which = 2 (16-bit storage
  * only, WAVE_EINVAL otherwise): the stored V^n = A^n - g A^{n-1}. */
 int wave_read_field(wave_t w, int32_t which, float *out_dev);
+
+/* Set a stored time level from in_dev (device float32 [nz][ny][nx]),
+ * float32 storage only (WAVE_EINVAL otherwise): which = 0 writes A^n, which =
+ * 1 the stored (undamped) A^{n-1}, so that the next wave_step advances from a
+ * given initial state (paper Sec. II's update applied to any wavefield; the
+ * inverse of wave_read_field).  The step counter is unchanged.  Enqueued on
+ * the context's stream; in_dev must stay valid until the stream reaches it. */
+int wave_write_field(wave_t w, int32_t which, const float *in_dev);
 
 /* Host copy of the step counter n (steps since the last reset). */
 int wave_time_index(wave_t w, int32_t *n);

@@ -1,7 +1,7 @@
 """Forward time stepping, written out literally (FP64).
 
-Sec. II: Eq. 1 is evaluated at every grid point and used to update the
-wavefield once per time iteration.  The paper does not name the integrator;
+Sec. II: Eq. 1 is evaluated at every grid point in each time step to advance
+the wavefield.  The paper does not name the integrator;
 the reading taken is the 2nd-order leapfrog of the constant-density acoustic
 equation u_tt = v^2 lap(u) + s(t) delta(x - x_s):
 

@@ -19,7 +19,7 @@ STORAGE = {"f32": WAVE_F32, "f16": WAVE_F16, "bf16": WAVE_BF16}
 # Every symbol include/wave.h declares.
 EXPORTS = (
     "wave_params_init", "wave_workspace_bytes", "wave_create", "wave_reset", "wave_step", "wave_run",
-    "wave_adjoint", "wave_read_field", "wave_time_index", "wave_state_bytes", "wave_save_state", "wave_load_state",
+    "wave_adjoint", "wave_read_field", "wave_write_field", "wave_time_index", "wave_state_bytes", "wave_save_state", "wave_load_state",
     "wave_sync_status", "wave_destroy", "wave_tiling",
     "wave_variant_count", "wave_variant_info", "wave_status_string",
 )
@@ -78,6 +78,7 @@ def lib():
         L.wave_run.argtypes = [vp, i32, vp, vp]
         L.wave_adjoint.argtypes = [vp, i32, vp, vp, vp]
         L.wave_read_field.argtypes = [vp, i32, vp]
+        L.wave_write_field.argtypes = [vp, i32, vp]
         L.wave_time_index.argtypes = [vp, P(i32)]
         L.wave_state_bytes.argtypes = [vp, P(ctypes.c_size_t)]
         L.wave_save_state.argtypes = [vp, vp]

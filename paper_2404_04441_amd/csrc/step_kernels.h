@@ -104,10 +104,12 @@ template <> struct Codec<kBF16> {
 template <typename T> __device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
 template <typename T> __device__ __forceinline__ void st_stream(T v, T *p) { __builtin_nontemporal_store(v, p); }
 
-// ---- buffer access: a per-plane resource (scalar base), a scalar byte offset
-// for the row and one 32-bit lane offset; every address used is inside the
-// array (rows, planes and columns are clamped), ghost values are selected
-// to zero where they are consumed.
+// ---- buffer access: raw buffer loads and stores through a resource (base
+// and size in bytes) with a scalar byte offset (the plane) and a 32-bit lane
+// offset (row and column).  Nothing is clamped: a node outside the grid gets
+// a lane offset past the end of the resource (kOOB below), for which the
+// hardware returns zero on a load and drops a store, so ghost nodes read as
+// the zero-Dirichlet exterior without selects or branches.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));

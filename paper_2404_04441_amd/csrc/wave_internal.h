@@ -130,8 +130,10 @@ hipError_t launch_decode_prev(int storage, const void *a, const void *v, float *
                               hipStream_t s);
 hipError_t launch_gather(int storage, const void *field, const int64_t *rec_lin, int nrec, float *traces,
                          const StepState *st, int k, hipStream_t s);
-hipError_t launch_scatter(float *field, const int64_t *rec_lin, int nrec, const float *m, const float *grec,
-                          const float *resid, int row, hipStream_t s);
+// field[node[u]] += g_u m (sum of the residuals of node u's receivers, summed
+// in receiver order): nodes u < nnode, their receivers ord[off[u] .. off[u+1])
+hipError_t launch_scatter(float *field, const int64_t *node, const int32_t *off, const int32_t *ord, int nnode,
+                          int nrec, const float *m, const float *gnode, const float *resid, int row, hipStream_t s);
 hipError_t launch_reset_state(StepState *st, hipStream_t s);
 hipError_t launch_set_n(StepState *st, int n, hipStream_t s);
 hipError_t launch_check_finite(int storage, const void *field, size_t n, StepState *st, hipStream_t s);

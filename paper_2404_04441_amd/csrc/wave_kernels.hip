@@ -422,13 +422,20 @@ __global__ void gather_kernel(const typename Codec<S>::raw *__restrict__ f, cons
   if (r < nrec) traces[static_cast<size_t>(n) * nrec + r] = Codec<S>::dec(f[lin[r]]) * inv;
 }
 
-__global__ void scatter_kernel(float *f, const int64_t *__restrict__ lin, int nrec, const float *__restrict__ m,
-                               const float *__restrict__ grec, const float *__restrict__ resid, int row) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < nrec) {
-    const int64_t p = lin[r];
-    atomicAdd(f + p, grec[r] * m[p] * resid[static_cast<size_t>(row) * nrec + r]);
-  }
+// Adjoint injection at an irregular receiver list: one thread per distinct
+// receiver node adds g m times the sum of that node's residuals, taken in
+// receiver order.  Each node is written by one thread and duplicates are
+// summed in a fixed order, so the result does not depend on scheduling.
+__global__ void scatter_kernel(float *f, const int64_t *__restrict__ node, const int32_t *__restrict__ off,
+                               const int32_t *__restrict__ ord, int nnode, int nrec, const float *__restrict__ m,
+                               const float *__restrict__ gnode, const float *__restrict__ resid, int row) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nnode) return;
+  const float *rr = resid + static_cast<size_t>(row) * nrec;
+  float sum = 0.f;
+  for (int j = off[u]; j < off[u + 1]; ++j) sum += rr[ord[j]];
+  const int64_t p = node[u];
+  f[p] = fmaf(gnode[u] * m[p], sum, f[p]);
 }
 
 template <int S>
@@ -565,9 +572,11 @@ hipError_t launch_gather(int storage, const void *field, const int64_t *lin, int
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(float *field, const int64_t *lin, int nrec, const float *m, const float *grec,
-                          const float *resid, int row, hipStream_t s) {
-  hipLaunchKernelGGL(scatter_kernel, dim3((nrec + 255) / 256), dim3(256), 0, s, field, lin, nrec, m, grec, resid, row);
+hipError_t launch_scatter(float *field, const int64_t *node, const int32_t *off, const int32_t *ord, int nnode,
+                          int nrec, const float *m, const float *gnode, const float *resid, int row, hipStream_t s) {
+  if (nnode <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_kernel, dim3((nnode + 255) / 256), dim3(256), 0, s, field, node, off, ord, nnode, nrec, m,
+                     gnode, resid, row);
   return hipGetLastError();
 }
 

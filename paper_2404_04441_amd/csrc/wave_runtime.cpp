@@ -28,7 +28,7 @@ constexpr double kD1[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct Layout {
-  size_t st, gx, gy, gz, rz, rec_lin, grec, m, fa, fb, fv, ckpt, seg, mua, mub, img;
+  size_t st, gx, gy, gz, rz, rec_lin, rec_node, rec_off, rec_ord, grec, m, fa, fb, fv, ckpt, seg, mua, mub, img;
   size_t cpml_ab, cpml_slab[3], total;  // CPML: a/b tables, psi+zeta slab pair per axis
   int K, nck;
 };
@@ -109,6 +109,11 @@ int plan(const wave_params *p, Layout *L) {
   L->gz = take(4 * (static_cast<size_t>(p->nz) + kPadZ));
   L->rz = take(4 * (static_cast<size_t>(p->nz) + kPadZ));
   L->rec_lin = take(8 * static_cast<size_t>(p->nrec));
+  // the receivers grouped by node (adjoint injection): distinct nodes, the
+  // offsets of each node's receivers in rec_ord, and the sponge factor per node
+  L->rec_node = take(8 * static_cast<size_t>(p->nrec));
+  L->rec_off = take(4 * (static_cast<size_t>(p->nrec) + 1));
+  L->rec_ord = take(4 * static_cast<size_t>(p->nrec));
   L->grec = take(4 * static_cast<size_t>(p->nrec));
   L->m = take(4 * Np);
   L->fa = take(es * Np);
@@ -258,12 +263,15 @@ struct wave_ctx {
   char *ws = nullptr;
   Layout L{};
   StepState *st = nullptr;
-  float *gx = nullptr, *gy = nullptr, *gz = nullptr, *m = nullptr, *grec = nullptr;
+  float *gx = nullptr, *gy = nullptr, *gz = nullptr, *m = nullptr, *grec = nullptr;  // grec: per receiver node
   int32_t *rz = nullptr;
   bool cpml = false;
   bool cpml_fused = false;  // the forward shape's step kernel applies the x part of the CPML terms
   CpmlArgs cp{};
-  int64_t *rec_lin = nullptr;
+  int64_t *rec_lin = nullptr;   // linear node index of each receiver (gather)
+  int64_t *rec_node = nullptr;  // distinct receiver nodes, ascending (adjoint injection)
+  int32_t *rec_off = nullptr, *rec_ord = nullptr;
+  int nrec_nodes = 0;
   void *fa = nullptr, *fb = nullptr, *fv = nullptr;
   size_t N = 0;   // interior nodes
   size_t Np = 0;  // nodes of a padded field (interior + kPadZ zero planes)
@@ -638,6 +646,9 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   w->gz = reinterpret_cast<float *>(w->ws + L.gz);
   w->rz = reinterpret_cast<int32_t *>(w->ws + L.rz);
   w->rec_lin = reinterpret_cast<int64_t *>(w->ws + L.rec_lin);
+  w->rec_node = reinterpret_cast<int64_t *>(w->ws + L.rec_node);
+  w->rec_off = reinterpret_cast<int32_t *>(w->ws + L.rec_off);
+  w->rec_ord = reinterpret_cast<int32_t *>(w->ws + L.rec_ord);
   w->grec = reinterpret_cast<float *>(w->ws + L.grec);
   w->m = reinterpret_cast<float *>(w->ws + L.m);
   w->fa = w->ws + L.fa;
@@ -663,12 +674,28 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   const std::vector<float> gy = sponge_table(ny, p->sponge_width, p->sponge_alpha);
   std::vector<float> gz = sponge_table(nz, p->sponge_width, p->sponge_alpha);
   std::vector<int64_t> lin(p->nrec);
-  std::vector<float> grec(p->nrec);
   for (int r = 0; r < p->nrec; ++r) {
     const int x = w->rec[3 * r], y = w->rec[3 * r + 1], z = w->rec[3 * r + 2];
     lin[r] = x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z);
-    grec[r] = static_cast<float>(static_cast<double>(gx[x]) * gy[y] * gz[z]);
   }
+  // receivers grouped by node, each group in receiver order: the adjoint
+  // sums a node's residuals in that fixed order (duplicates included)
+  std::vector<int32_t> ord(p->nrec), off;
+  std::vector<int64_t> node;
+  std::vector<float> grec;
+  for (int r = 0; r < p->nrec; ++r) ord[r] = r;
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return lin[a] < lin[b]; });
+  for (int j = 0; j < p->nrec; ++j) {
+    const int r = ord[j];
+    if (node.empty() || node.back() != lin[r]) {
+      const int x = w->rec[3 * r], y = w->rec[3 * r + 1], z = w->rec[3 * r + 2];
+      node.push_back(lin[r]);
+      off.push_back(j);
+      grec.push_back(static_cast<float>(static_cast<double>(gx[x]) * gy[y] * gz[z]));
+    }
+  }
+  off.push_back(p->nrec);
+  w->nrec_nodes = static_cast<int>(node.size());
   w->fused_rec = detect_box(w->rec, p->nrec, &w->box);
   if (!w->fused_rec) w->box = RecBox{};
   // receiver-box plane index of every z-plane (-1: no receivers there); the
@@ -695,6 +722,9 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   if (!rc) rc = hip_rc(hipMemcpyAsync(w->rz, rz.data(), 4 * rz.size(), hipMemcpyHostToDevice, w->stream));
   if (!rc && p->nrec > 0) {
     rc = hip_rc(hipMemcpyAsync(w->rec_lin, lin.data(), 8 * lin.size(), hipMemcpyHostToDevice, w->stream));
+    if (!rc) rc = hip_rc(hipMemcpyAsync(w->rec_node, node.data(), 8 * node.size(), hipMemcpyHostToDevice, w->stream));
+    if (!rc) rc = hip_rc(hipMemcpyAsync(w->rec_off, off.data(), 4 * off.size(), hipMemcpyHostToDevice, w->stream));
+    if (!rc) rc = hip_rc(hipMemcpyAsync(w->rec_ord, ord.data(), 4 * ord.size(), hipMemcpyHostToDevice, w->stream));
     if (!rc) rc = hip_rc(hipMemcpyAsync(w->grec, grec.data(), 4 * grec.size(), hipMemcpyHostToDevice, w->stream));
   }
   if (!rc) rc = hip_rc(launch_init_m(vel_dev, w->m, w->N, static_cast<float>(p->dt), w->st, w->stream));
@@ -821,7 +851,8 @@ int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *re
       b.resid_row = k - 1;
       rc = hip_rc(launch_step(WAVE_F32, w->adj.variant, true, b, w->stream));
       if (!rc && !w->fused_rec && w->p.nrec > 0)
-        rc = hip_rc(launch_scatter(mu2, w->rec_lin, w->p.nrec, w->m, w->grec, resid_dev, k - 1, w->stream));
+        rc = hip_rc(launch_scatter(mu2, w->rec_node, w->rec_off, w->rec_ord, w->nrec_nodes, w->p.nrec, w->m, w->grec,
+                                   resid_dev, k - 1, w->stream));
       std::swap(mu1, mu2);
     }
   }
@@ -843,6 +874,12 @@ int wave_read_field(wave_t w, int32_t which, float *out_dev) {
     return hip_rc(launch_decode(w->p.storage, w->field((w->n & 1) ^ 1), out_dev, w->N, w->st, 3, false, w->stream));
   return hip_rc(launch_decode_prev(w->p.storage, w->field(w->n & 1), w->fv, out_dev, w->gx, w->gy, w->gz, w->p.nx,
                                    w->p.ny, w->p.nz, w->st, w->stream));
+}
+
+int wave_write_field(wave_t w, int32_t which, const float *in_dev) {
+  if (!w || !in_dev || which < 0 || which > 1 || w->p.storage != WAVE_F32) return WAVE_EINVAL;
+  void *dst = w->field(which == 0 ? (w->n & 1) : ((w->n & 1) ^ 1));
+  return hip_rc(hipMemcpyAsync(dst, in_dev, 4 * w->N, hipMemcpyDeviceToDevice, w->stream));
 }
 
 // Snapshot layout: 256-B header | step state | A fields 0 and 1 | V (16-bit)

@@ -165,6 +165,14 @@ class Solver:
         L.check(L.lib().wave_read_field(self._h, int(which), _ptr(out)), "wave_read_field")
         return out
 
+    def write_field(self, which: int, field: torch.Tensor):
+        """Set A^n (which = 0) or the stored A^{n-1} (which = 1) from a float32
+        [nz, ny, nx] device tensor (float32 storage only)."""
+        _dev_f32(field, "field")
+        if tuple(field.shape) != self.shape:
+            raise ValueError(f"field must have shape {self.shape}")
+        L.check(L.lib().wave_write_field(self._h, int(which), _ptr(field)), "wave_write_field")
+
     def save_state(self, out=None) -> torch.Tensor:
         """Snapshot of the shot (device bytes) that ``load_state`` resumes from."""
         n = ctypes.c_size_t()

@@ -105,6 +105,7 @@ int main(void) {
   CHECK(wave_sync_status(NULL, &f) == WAVE_EINVAL && wave_step(NULL, 1, NULL, NULL) == WAVE_EINVAL);
   CHECK(wave_run(NULL, 1, NULL, NULL) == WAVE_EINVAL && wave_adjoint(NULL, 1, NULL, NULL, NULL) == WAVE_EINVAL);
   CHECK(wave_read_field(NULL, 0, NULL) == WAVE_EINVAL && wave_workspace_bytes(NULL, &b) == WAVE_EINVAL);
+  CHECK(wave_write_field(NULL, 0, NULL) == WAVE_EINVAL);
   int32_t tiling[3];
   CHECK(wave_tiling(NULL, tiling) == WAVE_EINVAL);
   wave_params_init(NULL);

@@ -156,6 +156,7 @@ def test_null_context_calls(lib):
     assert lib.wave_reset(None) == L.WAVE_EINVAL
     assert lib.wave_adjoint(None, 1, None, None, None) == L.WAVE_EINVAL
     assert lib.wave_read_field(None, 0, None) == L.WAVE_EINVAL
+    assert lib.wave_write_field(None, 0, None) == L.WAVE_EINVAL
     assert lib.wave_time_index(None, ctypes.byref(n)) == L.WAVE_EINVAL
     assert lib.wave_sync_status(None, ctypes.byref(f)) == L.WAVE_EINVAL
     assert lib.wave_destroy(None) == L.WAVE_EINVAL

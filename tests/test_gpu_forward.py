@@ -294,3 +294,107 @@ def test_full_size_512_sampled_one_step():
     _say(f"max sampled error / max|A| = {err:.3e}")
     assert scale > 0 and err <= 1e-6
     assert np.array_equal(row, A_np1[0].ravel())
+
+
+class _Gathered:
+    """A few nodes of a device array, gathered to the host: indexed [z, y, x]
+    like the array itself, for the oracle's pointwise step."""
+
+    def __init__(self, shape, table):
+        self.shape = shape
+        self._t = table
+
+    def __getitem__(self, idx):
+        return self._t[tuple(int(i) for i in idx)]
+
+
+def _random_state_one_step(W, vel_dev, seed, edge, **solver_kw):
+    """A^n and the stored A^{n-1} set to seeded random normal fields, so that
+    every tile edge and z-chunk boundary carries data; one GPU step from that
+    state is checked against the oracle's one-step formula at sampled nodes
+    (random, and on tile / chunk / sponge edges), and its trace row against
+    the new field at the receivers."""
+    from paper_2404_04441_amd import Solver
+
+    dev = vel_dev.device
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    A_n = torch.randn(W.shape, generator=gen, device=dev)
+    A_nm1 = torch.randn(W.shape, generator=gen, device=dev)
+    s = Solver(vel_dev, W.h, W.dt, src=W.src, rec=W.rec, sponge_width=W.sponge_width,
+               sponge_alpha=W.sponge_alpha, **solver_kw)
+    wav = torch.from_numpy(W.wavelet()).to(dev)
+    tr = torch.zeros((1, len(W.rec)), dtype=torch.float32, device=dev)
+    s.reset()
+    s.write_field(0, A_n)
+    s.write_field(1, A_nm1)
+    s.step(1, wav, tr)
+    A_np1 = s.read_field(0)
+    tiling = s.tiling()
+    s.close()
+    from paper_2404_04441_amd import variant_info
+
+    info = variant_info(tiling["variant"])
+    _say(f"tiling {tiling} {info}")
+    nz, ny, nx = W.shape
+    # nodes on both sides of every tile edge and z-chunk boundary of this configuration
+    tx = 64 * info["vec"] if info["family"] in (0, 3) else 64
+    ty = info["by"] * info["ry"] if info["family"] in (0, 3) else info["by"]
+    tz = tiling["zchunk"]
+
+    def around(step, n):
+        k = np.arange(step, n, step)
+        return np.concatenate([k - 1, k, edge[edge < n]])
+
+    ex, ey, ez = around(tx, nx), around(ty, ny), around(tz, nz)
+    rng = np.random.default_rng(seed)
+    pts = [np.stack([rng.integers(0, nx, 1500), rng.integers(0, ny, 1500), rng.integers(0, nz, 1500)], 1)]
+    pts.append(np.stack([rng.choice(ex, 3000), rng.choice(ey, 3000), rng.choice(ez, 3000)], 1))
+    pts.append(np.array([W.src]))
+    pts = np.concatenate(pts)
+    offs = [(0, 0, 0)] + [o for m in range(1, 5) for o in
+                          ((m, 0, 0), (-m, 0, 0), (0, m, 0), (0, -m, 0), (0, 0, m), (0, 0, -m))]
+    need = sorted({(z + dz, y + dy, x + dx) for x, y, z in pts for dx, dy, dz in offs
+                   if 0 <= x + dx < nx and 0 <= y + dy < ny and 0 <= z + dz < nz})
+    idx = torch.from_numpy(np.array(need, dtype=np.int64)).to(dev)
+    tables = [dict(zip(need, t[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy().tolist()))
+              for t in (A_n, A_nm1, vel_dev)]
+    an, ap, vv = (_Gathered(W.shape, t) for t in tables)
+    ref = oracle.step_at(pts, an, ap, vv, W.h, W.dt, src=W.src, s_n=float(wav[0]), sponge_width=W.sponge_width,
+                         sponge_alpha=W.sponge_alpha)
+    p = torch.from_numpy(pts.astype(np.int64)).to(dev)
+    got = A_np1[p[:, 2], p[:, 1], p[:, 0]].double().cpu().numpy()
+    scale = float(A_np1.abs().max())
+    err = np.abs(got - ref).max() / scale
+    _say(f"max sampled error / max|A| = {err:.3e} over {len(pts)} nodes")
+    assert scale > 0 and err <= 1e-6
+    r = torch.from_numpy(np.asarray(W.rec, dtype=np.int64)).to(dev)
+    assert torch.equal(tr[0], A_np1[r[:, 2], r[:, 1], r[:, 0]])
+
+
+def test_full_size_512_random_state_one_step():
+    """The 512^3 workload (sponge, source, receiver plane) in the benchmark's
+    configuration (the fixed rule's shape and z-chunk)."""
+    W = workload("large")
+    _say("case: 512^3 large workload, one step from a random state")
+    vel = torch.from_numpy(W.velocity()).cuda()
+    edge = np.array([0, 1, 3, 4, 19, 20, 21, 63, 64, 65, 255, 256, 257, 260, 261, 262, 447, 448, 491, 492, 507,
+                     508, 510, 511])
+    _random_state_one_step(W, vel, 512, edge, tune=False)
+
+
+def test_full_size_1024_random_state_one_step():
+    """The 1024^3 workload (smooth random model on the device, Dirichlet, line
+    of 1024 receivers) in the configuration the benchmark times for it
+    (create-time tuning; z-chunks capped so a workgroup's buffers span less
+    than 2 GiB)."""
+    from synth.velocity import smooth_random_torch
+
+    W = workload("precision")
+    _say("case: 1024^3 precision workload, one step from a random state")
+    vel = smooth_random_torch(W.shape, seed=3, device=torch.device("cuda"))
+    edge = np.array([0, 1, 3, 4, 5, 63, 64, 65, 127, 128, 129, 255, 256, 257, 459, 460, 461, 511, 512, 513, 767,
+                     768, 919, 920, 921, 1019, 1020, 1022, 1023])
+    _random_state_one_step(W, vel, 1024, edge)
+    del vel
+    torch.cuda.empty_cache()

@@ -30,11 +30,11 @@ torch = pytest.importorskip("torch")
 # (f16 field / traces) and 1.7e-4 / 5e-6 (bf16) on this case; the bounds are
 # about three times that.
 TOL_EMUL = {"f16": 3e-3, "bf16": 1e-3}
-# unquantized FP64 vs storage type on the 500-step 128^3 crop: the oracle's
-# own float32 loop sits at 1.9e-5 there and the emulated 16-bit schemes at
-# 2.9e-3 (f16) and 2.5e-2 (bf16); 16-bit bounds are sanity bounds only
-# (parity unpinned)
-BOUND_PLAIN = {"f32": 1e-4, "f16": 1e-2, "bf16": 1e-1}
+# unquantized FP64 vs storage type: the emulated 16-bit schemes sit at
+# 2.9e-3 (f16) and 2.5e-2 (bf16) on the 500-step 128^3 crop; these are sanity
+# bounds only (parity unpinned).  Float32 is bounded by the float32 floor
+# instead (test_precision_crop_float32_within_its_rounding_floor).
+BOUND_PLAIN = {"f16": 1e-2, "bf16": 1e-1}
 ULP = {"f16": 2.0 ** -10, "bf16": 2.0 ** -7}   # spacing relative to a normal value
 TINY = {"f16": 2.0 ** -24, "bf16": 2.0 ** -133}  # smallest subnormal
 
@@ -140,21 +140,49 @@ def test_one_step_encoding(fmt):
         assert np.abs(got[~live]).max(initial=0.0) <= 2.0 ** -99
 
 
-def test_precision_crop_error_report():
-    """The 128^3 crop of the 1024^3 workload, 500 steps, every storage type
-    against the unquantized FP64 oracle (the per-configuration error report)."""
+@functools.lru_cache(maxsize=None)
+def crop_reference(dtype_name="float64"):
+    """The oracle's loop on the 128^3 crop, 500 steps, in float64 (the
+    reference) or float32 (the rounding floor of float32 arithmetic)."""
     W = workload("precision_crop")
-    vel = W.velocity()
-    wav = W.wavelet()
-    _say("case: 128^3 crop, 500 steps, FP64 oracle")
-    ref = oracle.forward(vel, W.h, W.dt, W.src, wav, W.rec, nt=W.nt)
-    for fmt in ("f32", "f16", "bf16"):
-        got = gpu_run(vel, W.h, W.dt, W.src, wav, W.rec, W.nt, storage=fmt)
+    _say(f"case: 128^3 crop, 500 steps, oracle in {dtype_name}")
+    out = oracle.forward(W.velocity(), W.h, W.dt, W.src, W.wavelet(), W.rec, nt=W.nt, dtype=getattr(np, dtype_name))
+    return {"u": out["u"], "traces": out["traces"]}
+
+
+def test_precision_crop_16bit_error_report():
+    """The 128^3 crop of the 1024^3 workload, 500 steps, 16-bit storage
+    against the unquantized FP64 oracle (the per-configuration error report;
+    the bounds are sanity bounds, parity unpinned)."""
+    W = workload("precision_crop")
+    ref = crop_reference("float64")
+    for fmt in ("f16", "bf16"):
+        got = gpu_run(W.velocity(), W.h, W.dt, W.src, W.wavelet(), W.rec, W.nt, storage=fmt)
         e_u = oracle.rel_l2(got["u"], ref["u"])
         e_t = oracle.rel_l2(got["traces"], ref["traces"])
         _say(f"crop {fmt}: rel-L2 field {e_u:.3e} traces {e_t:.3e}")
         assert got["flags"] == 0
         assert e_u <= BOUND_PLAIN[fmt]
+
+
+def test_precision_crop_float32_within_its_rounding_floor():
+    """Float32 storage on the same crop: after 500 steps no float32 evaluation
+    order reaches 1e-5 of the FP64 result -- the oracle's own loop run in
+    float32 lands at ~1.9e-5 (the phase error of float32 rounding
+    accumulates over the run).  The GPU field must stay within 2.5x that
+    floor (and its traces within 2.5x the floor's traces)."""
+    W = workload("precision_crop")
+    ref = crop_reference("float64")
+    floor = crop_reference("float32")
+    f_u = oracle.rel_l2(floor["u"], ref["u"])
+    f_t = oracle.rel_l2(floor["traces"], ref["traces"])
+    got = gpu_run(W.velocity(), W.h, W.dt, W.src, W.wavelet(), W.rec, W.nt, storage="f32")
+    e_u = oracle.rel_l2(got["u"], ref["u"])
+    e_t = oracle.rel_l2(got["traces"], ref["traces"])
+    _say(f"crop f32: rel-L2 field {e_u:.3e} traces {e_t:.3e}; oracle float32 loop: field {f_u:.3e} "
+         f"traces {f_t:.3e}; ratio {e_u / f_u:.2f} / {e_t / f_t:.2f}")
+    assert got["flags"] == 0
+    assert e_u <= 2.5 * f_u and e_t <= 2.5 * f_t
 
 
 def test_storage_tile_variants_bitwise_identical():

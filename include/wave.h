@@ -146,6 +146,27 @@ int wave_workspace_bytes(const wave_params *p, size_t *bytes);
 int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t ws_bytes,
                 void *hip_stream, wave_t *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): wave_create
+ * with the workspace in the library's own static device array of
+ * WAVE_STATIC_BYTES bytes (64 MiB: a float32 128^3 forward shot fits) instead
+ * of a caller-allocated one.  Each GPU the library runs on holds one such
+ * array for the life of the process; the context uses the array of the
+ * device current in the calling thread, which must be hip_stream's device.
+ * The caller still passes the velocity and, to the other calls, the
+ * wavelet, traces, residual and gradient.  Differences from wave_create:
+ * tune is ignored (the fixed rule's shape; timing would create events) and
+ * graph_steps must be 0 (WAVE_EINVAL; graph instantiation allocates).  At
+ * most one static context may exist per device: a second wave_create_static
+ * there returns WAVE_ESTATE until the first is destroyed; wave_destroy of a
+ * static context synchronises its stream so that the next one starts on an
+ * idle array.  Work from any other source that writes the array while a
+ * static context's work is in flight on that device races with it.  Errors
+ * as wave_create, plus WAVE_ENOSPC when wave_workspace_bytes(p) exceeds
+ * WAVE_STATIC_BYTES and WAVE_ESTATE as above. */
+#define WAVE_STATIC_BYTES ((size_t)64 << 20)
+int wave_create_static(const wave_params *p, const float *vel_dev, void *hip_stream, wave_t *out);
+
 /* Zero the wavefields and the step counter n (enqueued on the stream). */
 int wave_reset(wave_t w);
 

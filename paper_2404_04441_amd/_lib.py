@@ -14,11 +14,13 @@ LIB_PATH = os.path.join(_HERE, "libwave.so")
 WAVE_OK, WAVE_EINVAL, WAVE_EUNSTABLE, WAVE_ENOSPC, WAVE_EHIP, WAVE_ESTATE = 0, -1, -2, -3, -4, -5
 WAVE_F32, WAVE_F16, WAVE_BF16 = 0, 1, 2
 WAVE_FLAG_NONFINITE = 1
+WAVE_STATIC_BYTES = 64 << 20  # size of the static workspace of wave_create_static
 STORAGE = {"f32": WAVE_F32, "f16": WAVE_F16, "bf16": WAVE_BF16}
 
 # Every symbol include/wave.h declares.
 EXPORTS = (
-    "wave_params_init", "wave_workspace_bytes", "wave_create", "wave_reset", "wave_step", "wave_run",
+    "wave_params_init", "wave_workspace_bytes", "wave_create", "wave_create_static",
+    "wave_reset", "wave_step", "wave_run",
     "wave_adjoint", "wave_read_field", "wave_write_field", "wave_time_index", "wave_state_bytes", "wave_save_state", "wave_load_state",
     "wave_sync_status", "wave_destroy", "wave_tiling",
     "wave_variant_count", "wave_variant_info", "wave_status_string",
@@ -73,6 +75,7 @@ def lib():
         L.wave_params_init.restype = None
         L.wave_workspace_bytes.argtypes = [P(WaveParams), P(sz)]
         L.wave_create.argtypes = [P(WaveParams), vp, vp, sz, vp, P(vp)]
+        L.wave_create_static.argtypes = [P(WaveParams), vp, vp, P(vp)]
         L.wave_reset.argtypes = [vp]
         L.wave_step.argtypes = [vp, i32, vp, vp]
         L.wave_run.argtypes = [vp, i32, vp, vp]

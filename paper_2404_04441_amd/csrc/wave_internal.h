@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "wave.h"
+
 namespace wave {
 
 constexpr int kRadius = 4;   // stencil half-width (8th order)
@@ -147,5 +149,12 @@ hipError_t launch_cpml_psi(const CpmlArgs &c, const float *cur, hipStream_t s);
 // z-layer planes and y-layer rows of that shell (the x part is fused in the step)
 hipError_t launch_cpml_fix(const CpmlArgs &c, const float *cur, const float *m, float *out, bool yz_only,
                            hipStream_t s);
+
+// wave_create with the workspace in a device's static scratch array
+// (scratch_bytes long): at most one such context per device at a time
+// (WAVE_ESTATE otherwise); tuning off; graph_steps must be 0.  wave_destroy
+// of that context synchronises its stream and frees the device's slot.
+int create_static_ctx(const wave_params *p, const float *vel_dev, void *scratch, size_t scratch_bytes,
+                      void *hip_stream, wave_t *out, int device);
 
 }  // namespace wave

@@ -286,6 +286,7 @@ struct wave_ctx {
   const float *g_wavelet = nullptr;
   float *g_traces = nullptr;
 
+  int static_dev = -1;  // >= 0: the context lives in that device's static scratch array
   ~wave_ctx() { drop_graphs(); }
   void drop_graphs() {
     for (auto &g : graph)
@@ -597,6 +598,9 @@ int setup_cpml(wave_ctx *w, float vmax) {
   return rc;
 }
 
+int create_ctx(const wave_params *p, const float *vel_dev, void *ws_dev, size_t ws_bytes, void *hip_stream,
+               wave_t *out, int static_dev);
+
 }  // namespace
 
 extern "C" {
@@ -624,6 +628,15 @@ int wave_workspace_bytes(const wave_params *p, size_t *bytes) {
 
 int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t ws_bytes, void *hip_stream,
                 wave_t *out) {
+  return create_ctx(p, vel_dev, ws_dev, ws_bytes, hip_stream, out, -1);
+}
+
+}  // extern "C"
+
+namespace {
+
+int create_ctx(const wave_params *p, const float *vel_dev, void *ws_dev, size_t ws_bytes, void *hip_stream,
+               wave_t *out, int static_dev) {
   if (!out || !vel_dev || !ws_dev) return WAVE_EINVAL;
   *out = nullptr;
   Layout L;
@@ -634,6 +647,7 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
 
   wave_ctx *w = new (std::nothrow) wave_ctx();
   if (!w) return WAVE_EINVAL;
+  w->static_dev = static_dev;
   w->p = *p;
   w->rec.assign(p->rec, p->rec + 3 * static_cast<size_t>(p->nrec));
   w->p.rec = nullptr;  // never keep the caller's pointer
@@ -758,6 +772,39 @@ int wave_create(const wave_params *p, const float *vel_dev, void *ws_dev, size_t
   *out = w;
   return WAVE_OK;
 }
+
+}  // namespace
+
+// A context in a device's static scratch array (the library's own memory):
+// at most one per device at a time.
+namespace {
+std::mutex g_static_mu;
+constexpr int kMaxStaticDevices = 64;
+bool g_static_live[kMaxStaticDevices] = {};
+}  // namespace
+
+int wave::create_static_ctx(const wave_params *p, const float *vel_dev, void *scratch, size_t scratch_bytes,
+                            void *hip_stream, wave_t *out, int device) {
+  if (!p || !out || device < 0 || device >= kMaxStaticDevices) return WAVE_EINVAL;
+  *out = nullptr;
+  // no graph capture (instantiation allocates) and no tuning (its events)
+  if (p->graph_steps != 0) return WAVE_EINVAL;
+  wave_params q = *p;
+  q.tune = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_live[device]) return WAVE_ESTATE;
+    g_static_live[device] = true;
+  }
+  const int rc = create_ctx(&q, vel_dev, scratch, scratch_bytes, hip_stream, out, device);
+  if (rc) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_live[device] = false;
+  }
+  return rc;
+}
+
+extern "C" {
 
 int wave_reset(wave_t w) {
   if (!w) return WAVE_EINVAL;
@@ -988,8 +1035,19 @@ int wave_sync_status(wave_t w, uint32_t *flags) {
 
 int wave_destroy(wave_t w) {
   if (!w) return WAVE_EINVAL;
+  int rc = WAVE_OK;
+  const int dev = w->static_dev;
+  if (dev >= 0) {
+    // the next static context on this device reuses the same memory: let
+    // this one's queued work finish first
+    rc = hip_rc(hipStreamSynchronize(w->stream));
+  }
   delete w;
-  return WAVE_OK;
+  if (dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_live[dev] = false;
+  }
+  return rc;
 }
 
 int wave_variant_count(void) { return variant_count(); }

@@ -201,3 +201,23 @@ def test_variant_info_and_shape_validation(lib):
     assert lib.wave_variant_info(n, info) == L.WAVE_EINVAL
     assert lib.wave_variant_info(-1, info) == L.WAVE_EINVAL
     assert lib.wave_variant_info(0, None) == L.WAVE_EINVAL
+
+
+def test_static_workspace_size_checked_before_the_device(lib):
+    """wave_create_static refuses a workspace larger than its static array
+    (and graph replay) without touching a GPU."""
+    p = L.WaveParams()
+    lib.wave_params_init(ctypes.byref(p))
+    p.nx = p.ny = p.nz = 512
+    p.dt = 1e-4
+    b = ctypes.c_size_t()
+    assert lib.wave_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == L.WAVE_OK
+    assert b.value > L.WAVE_STATIC_BYTES
+    h = ctypes.c_void_p()
+    fake_vel = ctypes.c_void_p(256)  # never dereferenced: the size check comes first
+    assert lib.wave_create_static(ctypes.byref(p), fake_vel, None, ctypes.byref(h)) == L.WAVE_ENOSPC
+    p.nx = p.ny = p.nz = 16
+    p.graph_steps = 4
+    assert lib.wave_create_static(ctypes.byref(p), fake_vel, None, ctypes.byref(h)) == L.WAVE_EINVAL
+    assert lib.wave_create_static(None, fake_vel, None, ctypes.byref(h)) == L.WAVE_EINVAL
+    assert not h.value

@@ -93,11 +93,8 @@ template <> struct Codec<kF16> {
 template <> struct Codec<kBF16> {
   using raw = uint16_t;
   __device__ static float dec(raw r) { return __uint_as_float(static_cast<uint32_t>(r) << 16); }
-  __device__ static raw enc(float x) {  // round to nearest even on the float32 bits
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<raw>((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return static_cast<raw>(u >> 16);
+  __device__ static raw enc(float x) {  // round to nearest even: gfx950's v_cvt_pk_bf16_f32
+    return __builtin_bit_cast(uint16_t, static_cast<__bf16>(x));
   }
 };
 
@@ -586,9 +583,10 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       for (int j = 0; j < RY; ++j)
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
-          float t = a.c.kz[R - 1] * q[k - R][j][i];
+          const float c = q[k][j][i];
+          float t = a.c.kz[R - 1] * (q[k - R][j][i] - c);
 #pragma unroll
-          for (int m = R - 1; m >= 1; --m) t = fmaf(a.c.kz[m - 1], q[k - m][j][i], t);
+          for (int m = R - 1; m >= 1; --m) t = fmaf(a.c.kz[m - 1], q[k - m][j][i] - c, t);
           X[k][j][i] = t;
         }
   }
@@ -615,11 +613,10 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       if (VEC > 1 || k != R) lds_get<VEC>(row + VEC * k, win + VEC * k);
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
-      if (VEC == 1) win[R] = Q[cs][j][0];
-      lap[i] = a.c.k0 * Q[cs][j][i];
+      lap[i] = 0.f;
       if constexpr (CP) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) lax[d][i] = a.c.k0a[d] * Q[cs][j][i];
+        for (int d = 0; d < 3; ++d) lax[d][i] = 0.f;
       }
     }
 #pragma unroll
@@ -639,15 +636,19 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       }
 #pragma unroll
       for (int i = 0; i < VEC; ++i) {
+        // second differences from the centre: (u(+m) - u) + (u(-m) - u)
+        const float c = Q[cs][j][i];
+        const float sx = (win[R + i + m] - c) + (win[R + i - m] - c);
+        const float sy = (yp[i] - c) + (ym[i] - c);
+        const float sz = (Q[(s0 + R + m) % kQ][j][i] - c) + (Q[(s0 + R - m + kQ) % kQ][j][i] - c);
         if constexpr (CP) {
-          lax[0][i] = fmaf(a.c.kx[m - 1], win[R + i + m] + win[R + i - m], lax[0][i]);
-          lax[1][i] = fmaf(a.c.ky[m - 1], yp[i] + ym[i], lax[1][i]);
-          lax[2][i] = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i] + Q[(s0 + R - m + kQ) % kQ][j][i], lax[2][i]);
+          lax[0][i] = fmaf(a.c.kx[m - 1], sx, lax[0][i]);
+          lax[1][i] = fmaf(a.c.ky[m - 1], sy, lax[1][i]);
+          lax[2][i] = fmaf(a.c.kz[m - 1], sz, lax[2][i]);
         } else {
-          lap[i] = fmaf(a.c.kx[m - 1], win[R + i + m] + win[R + i - m], lap[i]);
-          lap[i] = fmaf(a.c.ky[m - 1], yp[i] + ym[i], lap[i]);
-          if constexpr (!SEMI)
-            lap[i] = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i] + Q[(s0 + R - m + kQ) % kQ][j][i], lap[i]);
+          lap[i] = fmaf(a.c.kx[m - 1], sx, lap[i]);
+          lap[i] = fmaf(a.c.ky[m - 1], sy, lap[i]);
+          if constexpr (!SEMI) lap[i] = fmaf(a.c.kz[m - 1], sz, lap[i]);
         }
       }
     }
@@ -660,7 +661,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       for (int i = 0; i < VEC; ++i) {
         float t = Xp[cs][j][i];
 #pragma unroll
-        for (int m = 1; m <= R; ++m) t = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i], t);
+        for (int m = 1; m <= R; ++m) t = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i] - Q[cs][j][i], t);
         lap[i] += t;
       }
     }
@@ -686,9 +687,10 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
         if constexpr (SEMI) {  // left half of plane z+R from planes z .. z+R-1
 #pragma unroll
           for (int i = 0; i < VEC; ++i) {
-            float t = a.c.kz[R - 1] * q[cslot][j][i];
+            const float c = q[(s + 2 * R) % kQ][j][i];
+            float t = a.c.kz[R - 1] * (q[cslot][j][i] - c);
 #pragma unroll
-            for (int m = R - 1; m >= 1; --m) t = fmaf(a.c.kz[m - 1], q[(s + 2 * R - m) % kQ][j][i], t);
+            for (int m = R - 1; m >= 1; --m) t = fmaf(a.c.kz[m - 1], q[(s + 2 * R - m) % kQ][j][i] - c, t);
             X[(s + 2 * R) % kQ][j][i] = t;
           }
         }
@@ -956,12 +958,12 @@ __global__ void __launch_bounds__(64 * BY * BZ) gmem_kernel(StepArgs a) {
   const int x = b.x, y = b.y, z = b.z;
   const uint32_t own = node_off(x, y, z, nx, ny, b.zlo);
   const float c = U(x, y, z);
-  float lap = a.c.k0 * c;
+  float lap = 0.f;
 #pragma unroll
   for (int m = 1; m <= R; ++m) {
-    lap = fmaf(a.c.kx[m - 1], U(x + m, y, z) + U(x - m, y, z), lap);
-    lap = fmaf(a.c.ky[m - 1], U(x, y + m, z) + U(x, y - m, z), lap);
-    lap = fmaf(a.c.kz[m - 1], U(x, y, z + m) + U(x, y, z - m), lap);
+    lap = fmaf(a.c.kx[m - 1], (U(x + m, y, z) - c) + (U(x - m, y, z) - c), lap);
+    lap = fmaf(a.c.ky[m - 1], (U(x, y + m, z) - c) + (U(x, y - m, z) - c), lap);
+    lap = fmaf(a.c.kz[m - 1], (U(x, y, z + m) - c) + (U(x, y, z - m) - c), lap);
   }
   const float pc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rP, static_cast<int>(own), 0, kNT));
   const float mc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rM, static_cast<int>(own), 0, kNT));
@@ -996,12 +998,12 @@ __global__ void __launch_bounds__(64 * BY * BZ) smem_kernel(StepArgs a) {
             tz = static_cast<int>(threadIdx.x) / (64 * BY);
   const int cx = tx + R, cy = ty + R, cz = tz + R;
   const float c = T[cz][cy][cx];
-  float lap = a.c.k0 * c;
+  float lap = 0.f;
 #pragma unroll
   for (int m = 1; m <= R; ++m) {
-    lap = fmaf(a.c.kx[m - 1], T[cz][cy][cx + m] + T[cz][cy][cx - m], lap);
-    lap = fmaf(a.c.ky[m - 1], T[cz][cy + m][cx] + T[cz][cy - m][cx], lap);
-    lap = fmaf(a.c.kz[m - 1], T[cz + m][cy][cx] + T[cz - m][cy][cx], lap);
+    lap = fmaf(a.c.kx[m - 1], (T[cz][cy][cx + m] - c) + (T[cz][cy][cx - m] - c), lap);
+    lap = fmaf(a.c.ky[m - 1], (T[cz][cy + m][cx] - c) + (T[cz][cy - m][cx] - c), lap);
+    lap = fmaf(a.c.kz[m - 1], (T[cz + m][cy][cx] - c) + (T[cz - m][cy][cx] - c), lap);
   }
   const uint32_t own = node_off(b.x, b.y, b.z, nx, ny, b.zlo);
   const float pc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rP, static_cast<int>(own), 0, kNT));

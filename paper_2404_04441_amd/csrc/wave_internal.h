@@ -32,12 +32,15 @@ struct StepState {
 };
 static_assert(sizeof(StepState) == 128, "state block layout");
 
+// Weights of the Laplacian of Eq. 1.  The kernels evaluate it as second
+// differences from the centre, sum_a sum_m k_am ((u(+m) - u) + (u(-m) - u)):
+// with c0 = -2 sum_m c_m this is the same operator, but no large centre term
+// is summed against its neighbours (in float32 that cancellation dominated
+// the rounding error of a long run; see the tolerance notes in the tests).
 struct Coef {
-  float k0;        // c0 * (1/dx^2 + 1/dy^2 + 1/dz^2)
-  float kx[4];     // c_m / dx^2
+  float kx[4];     // c_m / dx^2, m = 1..4
   float ky[4];
   float kz[4];
-  float k0a[3];    // c0 / h_a^2 per axis (the CPML form needs the per-axis second derivatives)
 };
 
 // Receivers forming a regular box, listed x fastest then y then z:
@@ -60,7 +63,8 @@ struct CpmlArgs {
   const float *ca[3];        // a coefficient per node along each axis (n_a entries)
   const float *cb[3];        // b coefficient
   float d1w[3][4];           // w_m / h_a (first derivative)
-  float d2w[3][5];           // c_m / h_a^2 (second derivative, c_0 first)
+  float d2w[3][5];           // c_m / h_a^2 (second derivative; [0] = c_0 / h_a^2 is implied by the
+                             // centred second differences and not read)
   int W;                     // layer width in nodes (2W <= every axis)
   int nx, ny, nz;
 };

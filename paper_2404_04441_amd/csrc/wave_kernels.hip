@@ -252,16 +252,16 @@ __global__ void __launch_bounds__(256) cpml_fix_yz_kernel(CpmlArgs c, const floa
     float cc[VEC], d2[VEC];
     vload<VEC>(cur + o, cc);
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) d2[e] = c.d2w[a][0] * cc[e];
+    for (int e = 0; e < VEC; ++e) d2[e] = 0.f;
 #pragma unroll
-    for (int k = 1; k <= R; ++k) {
+    for (int k = 1; k <= R; ++k) {  // second differences from the centre, as in the step kernel
       float up[VEC], dn[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) up[e] = dn[e] = 0.f;
       if (i + k < n) vload<VEC>(cur + o + k * stride, up);
       if (i - k >= 0) vload<VEC>(cur + o - k * stride, dn);
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) d2[e] = fmaf(c.d2w[a][k], up[e] + dn[e], d2[e]);
+      for (int e = 0; e < VEC; ++e) d2[e] = fmaf(c.d2w[a][k], (up[e] - cc[e]) + (dn[e] - cc[e]), d2[e]);
     }
     float *ze = c.zeta[a] + slab(s);
     float zv[VEC];
@@ -308,9 +308,10 @@ __global__ void __launch_bounds__(256) cpml_fix_kernel(CpmlArgs c, const float *
       extra += dpsi;
       continue;
     }
-    float d2 = c.d2w[a][0] * cur[o];
+    const float cc = cur[o];
+    float d2 = 0.f;
 #pragma unroll
-    for (int k = 1; k <= R; ++k) d2 = fmaf(c.d2w[a][k], cur_k(cur, o, A, k) + cur_k(cur, o, A, -k), d2);
+    for (int k = 1; k <= R; ++k) d2 = fmaf(c.d2w[a][k], (cur_k(cur, o, A, k) - cc) + (cur_k(cur, o, A, -k) - cc), d2);
     float *ze = c.zeta[a] + A.slab_rest + static_cast<unsigned>(s) * A.slab_stride;
     const float zn = fmaf(c.cb[a][A.i], *ze, c.ca[a][A.i] * (d2 + dpsi));
     *ze = zn;

@@ -32,8 +32,8 @@ torch = pytest.importorskip("torch")
 TOL_EMUL = {"f16": 3e-3, "bf16": 1e-3}
 # unquantized FP64 vs storage type: the emulated 16-bit schemes sit at
 # 2.9e-3 (f16) and 2.5e-2 (bf16) on the 500-step 128^3 crop; these are sanity
-# bounds only (parity unpinned).  Float32 is bounded by the float32 floor
-# instead (test_precision_crop_float32_within_its_rounding_floor).
+# bounds only (parity unpinned).  Float32 is held to 1e-5 there
+# (test_precision_crop_float32_within_1e5).
 BOUND_PLAIN = {"f16": 1e-2, "bf16": 1e-1}
 ULP = {"f16": 2.0 ** -10, "bf16": 2.0 ** -7}   # spacing relative to a normal value
 TINY = {"f16": 2.0 ** -24, "bf16": 2.0 ** -133}  # smallest subnormal
@@ -86,13 +86,34 @@ def test_storage_matches_emulated_scheme(fmt):
     assert e_plain <= BOUND_PLAIN[fmt]
 
 
+def _stencil_terms(A, h):
+    """sum_a sum_m |c_m| / h_a^2 (|A(+m) - A| + |A(-m) - A|) at every node:
+    the size of the terms a float32 evaluation of the Laplacian sums."""
+    c = oracle.second_derivative_weights(4)
+    hx, hy, hz = h
+    P = np.pad(A, 4)
+    core = (slice(4, -4),) * 3
+    out = np.zeros_like(A)
+    for axis, ha in ((2, hx), (1, hy), (0, hz)):
+        for m in range(1, 5):
+            for sgn in (1, -1):
+                sl = [slice(4, -4)] * 3
+                sl[axis] = slice(4 + sgn * m, P.shape[axis] - 4 + sgn * m)
+                out += abs(c[m]) / (ha * ha) * np.abs(P[tuple(sl)] - P[core])
+    return out
+
+
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
 def test_one_step_encoding(fmt):
     """From the GPU's own decoded A^n and V^n, the oracle computes one step in
     FP64 (V+ = g(V + m L A + q), A+ = g A + V+), picks both exponents from
     the bounds and rounds: the GPU's stored A^{n+1} and V^{n+1} must use the
-    same exponents and equal those values except for rare one-ulp flips
-    (float32 vs float64 before rounding)."""
+    same exponents and equal those values except for rare flips where the
+    float32 value before rounding differs from the float64 one.  Two values
+    delta apart round at most delta + one ulp apart, and the float32
+    evaluation is off by at most 16 float32 roundings of the size of its
+    terms (|V|, m times the stencil's terms, |q|, and g|A| for A): where
+    V + m L A nearly cancels that exceeds one ulp of the small result."""
     from oracle.storage import growth_bound_gamma, quantize, scale_exponent
     from paper_2404_04441_amd import Solver
 
@@ -119,10 +140,12 @@ def test_one_step_encoding(fmt):
     q[src[2], src[1], src[0]] = dt * dt * float(wav[40]) / (hx * hy * hz)
     v_new = G * (V + M * oracle.laplacian(A, h) + q)
     a_new = G * A + v_new
+    terms_v = G * (np.abs(V) + M * _stencil_terms(A, h) + np.abs(q))
+    terms_a = G * np.abs(A) + terms_v
     gamma = growth_bound_gamma(float(vel.max()), h, dt)
     bv = np.abs(V).max() + gamma * np.abs(A).max() + abs(q).max()
-    for name, got, exact, e in (("A", got_a, a_new, scale_exponent(np.abs(A).max() + bv)),
-                                ("V", got_v, v_new, scale_exponent(bv))):
+    for name, got, exact, e, terms in (("A", got_a, a_new, scale_exponent(np.abs(A).max() + bv), terms_a),
+                                       ("V", got_v, v_new, scale_exponent(bv), terms_v)):
         emu = quantize(exact * 2.0 ** e, fmt) * 2.0 ** -e
         scaled = got * 2.0 ** e
         assert np.array_equal(quantize(scaled, fmt), scaled)  # values on the format's grid
@@ -133,8 +156,12 @@ def test_one_step_encoding(fmt):
         diff = (got != emu) & live
         frac = diff.sum() / live.sum()
         step = np.maximum(ULP[fmt] * np.abs(emu * 2.0 ** e), TINY[fmt])
-        worst = (np.abs(got - emu) * 2.0 ** e / step)[live].max()
-        _say(f"{fmt} {name}: exponent {e}, {diff.sum()} of {live.sum()} live values differ, worst {worst:.2f} ulp")
+        slack = 16 * 2.0 ** -24 * terms * 2.0 ** e  # float32 evaluation, scaled units
+        dist = np.abs(got - emu) * 2.0 ** e
+        worst_ulp = (dist / step)[live].max()
+        worst = (dist / (step + slack))[live].max()
+        _say(f"{fmt} {name}: exponent {e}, {diff.sum()} of {live.sum()} live values differ, worst {worst_ulp:.2f} "
+             f"ulp, {worst:.2f} of (ulp + float32 evaluation bound)")
         assert live.sum() > 1000
         assert frac <= 1e-2 and worst <= 1.0 + 1e-9
         assert np.abs(got[~live]).max(initial=0.0) <= 2.0 ** -99
@@ -143,7 +170,7 @@ def test_one_step_encoding(fmt):
 @functools.lru_cache(maxsize=None)
 def crop_reference(dtype_name="float64"):
     """The oracle's loop on the 128^3 crop, 500 steps, in float64 (the
-    reference) or float32 (the rounding floor of float32 arithmetic)."""
+    reference) or float32 (the plain float32 loop, for comparison)."""
     W = workload("precision_crop")
     _say(f"case: 128^3 crop, 500 steps, oracle in {dtype_name}")
     out = oracle.forward(W.velocity(), W.h, W.dt, W.src, W.wavelet(), W.rec, nt=W.nt, dtype=getattr(np, dtype_name))
@@ -165,24 +192,25 @@ def test_precision_crop_16bit_error_report():
         assert e_u <= BOUND_PLAIN[fmt]
 
 
-def test_precision_crop_float32_within_its_rounding_floor():
-    """Float32 storage on the same crop: after 500 steps no float32 evaluation
-    order reaches 1e-5 of the FP64 result -- the oracle's own loop run in
-    float32 lands at ~1.9e-5 (the phase error of float32 rounding
-    accumulates over the run).  The GPU field must stay within 2.5x that
-    floor (and its traces within 2.5x the floor's traces)."""
+def test_precision_crop_float32_within_1e5():
+    """Float32 storage on the same crop: rel-L2 <= 1e-5 against FP64 after
+    the 500-step run, field and traces.  The step kernel sums the Laplacian
+    as second differences from the centre; the plain float32 loop (the
+    oracle's, summing the centre term against its neighbours) lands at
+    ~1.9e-5 here, and the GPU must also stay below it."""
     W = workload("precision_crop")
     ref = crop_reference("float64")
-    floor = crop_reference("float32")
-    f_u = oracle.rel_l2(floor["u"], ref["u"])
-    f_t = oracle.rel_l2(floor["traces"], ref["traces"])
+    loop32 = crop_reference("float32")
+    f_u = oracle.rel_l2(loop32["u"], ref["u"])
+    f_t = oracle.rel_l2(loop32["traces"], ref["traces"])
     got = gpu_run(W.velocity(), W.h, W.dt, W.src, W.wavelet(), W.rec, W.nt, storage="f32")
     e_u = oracle.rel_l2(got["u"], ref["u"])
     e_t = oracle.rel_l2(got["traces"], ref["traces"])
-    _say(f"crop f32: rel-L2 field {e_u:.3e} traces {e_t:.3e}; oracle float32 loop: field {f_u:.3e} "
-         f"traces {f_t:.3e}; ratio {e_u / f_u:.2f} / {e_t / f_t:.2f}")
+    _say(f"crop f32: rel-L2 field {e_u:.3e} traces {e_t:.3e}; plain float32 loop: field {f_u:.3e} "
+         f"traces {f_t:.3e}")
     assert got["flags"] == 0
-    assert e_u <= 2.5 * f_u and e_t <= 2.5 * f_t
+    assert e_u <= 1e-5 and e_t <= 1e-5
+    assert e_u <= f_u and e_t <= f_t
 
 
 def test_storage_tile_variants_bitwise_identical():

@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -327,19 +329,73 @@ def gradient_leg() -> dict:
             "misfit": misfit, "grad_finite": bool(torch.isfinite(grad).all().item())}
 
 
-def serving_leg(count: int) -> dict:
-    """Serve the first `count` requests of the seeded Poisson stream (20 req/s;
-    grids 128^3 .. 384^3, 500..2000 steps, f32 or f16 storage)."""
+def serving_leg(count: int, lanes: int = 0, slots: int = 8) -> dict:
+    """Serve the seeded Poisson stream of forward-shot requests (512 at 20/s;
+    grids 128^3 .. 384^3, 500..2000 steps, f32 or f16 storage).  Each grid
+    class is tuned once before the stream starts; admission is bounded by the
+    device memory free at that point (less a 4 GiB reserve)."""
+    import time as _t
+
+    import torch
+
     from paper_2404_04441_amd.serve import GpuBackend, ShotServer, requests_from_workload, summarize
 
     reqs = requests_from_workload(count)
-    print(f"[bench] serving {count} shot requests", file=sys.stderr, flush=True)
-    server = ShotServer(GpuBackend(graph_steps=20), budget_bytes=200 << 30, max_slots=8, chunk_steps=200)
+    backend = GpuBackend(graph_steps=20, lanes=lanes)
+    t0 = _t.perf_counter()
+    tuned = backend.pretune(reqs)
+    t_tune = _t.perf_counter() - t0
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    budget = max(free - (4 << 30), 1 << 30)
+    print(f"[bench] serving {count} shot requests; tuned {len(tuned)} classes in {t_tune:.1f} s; "
+          f"admission budget {budget / 2**30:.1f} GiB of {total / 2**30:.1f}", file=sys.stderr, flush=True)
+    server = ShotServer(backend, budget_bytes=budget, max_slots=slots, chunk_steps=200)
     res = server.run(reqs)
     out = summarize(res, reqs, server.elapsed)
     out["max_concurrent"] = server.max_concurrent
-    out["workload"] = f"first {count} of 512 Poisson shot requests at 20/s"
+    out["slots"] = slots
+    out["lanes"] = lanes
+    out["budget_gib"] = round(budget / 2**30, 1)
+    out["pretune_s"] = round(t_tune, 2)
+    out["workload"] = (f"{count} Poisson shot requests at 20/s (seed 5): grids 128^3, 256x192x128, 256^3, 384^3; "
+                       f"500..2000 steps; f32 or f16 storage; 20-node sponge; line of receivers")
     print(f"[bench] serving done: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def small_shot_probe(nt: int = 2000) -> dict:
+    """One 128^3 serving shot alone (f32, sponge, line of receivers), stepped
+    by graph replay as the server does: wall time per step.  Compared with
+    the step kernel's own duration (rocprofv3 kernel trace of this leg) it
+    shows how much of a small shot's time is launch overhead."""
+    import torch
+
+    from paper_2404_04441_amd import Solver
+    from paper_2404_04441_amd.serve import requests_from_workload
+
+    req = next(r for r in requests_from_workload(512) if r.shape == (128, 128, 128) and r.storage == "f32")
+    dev = torch.device("cuda:0")
+    vel = torch.from_numpy(np.ascontiguousarray(req.velocity, dtype=np.float32)).to(dev)
+    vel = vel.view(-1, 1, 1).expand(req.shape).contiguous()
+    from synth.wavelet import ricker
+    wav = torch.from_numpy(ricker(nt, req.dt, req.f0, req.t0)).to(dev)
+    tr = torch.empty((nt, len(req.rec)), dtype=torch.float32, device=dev)
+    out = {"grid": "128^3 f32, sponge 20, line of 128 receivers", "steps": nt}
+    for graph in (0, 20):
+        s = Solver(vel, req.h, req.dt, src=req.src, rec=req.rec, sponge_width=req.sponge_width,
+                   sponge_alpha=req.sponge_alpha, graph_steps=graph)
+        s.run(nt, wav, tr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            s.run(nt, wav, tr)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 3 / nt * 1e3
+        out[f"ms_per_step_graph{graph}"] = round(ms, 5)
+        out["tiling"] = s.tiling()
+        s.close()
+    print(f"[bench] small-shot probe: {out}", file=sys.stderr, flush=True)
     return out
 
 
@@ -359,8 +415,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the 16-bit, CPML, 1024^3, kernel-study and gradient measurements")
-    ap.add_argument("--serving", type=int, default=64,
+    ap.add_argument("--serving", type=int, default=512,
                     help="requests of the Poisson shot stream to serve after the throughput run (0: skip)")
+    ap.add_argument("--serving-lanes", type=int, default=0,
+                    help="serving: 0 = shots' kernels overlap freely; k = at most k kernels in flight")
+    ap.add_argument("--serving-slots", type=int, default=8, help="serving: shots admitted at once")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving leg and the small-shot probe and print their JSON")
     ap.add_argument("--study-only", action="store_true",
                     help="run only the 1024^3 kernel study (3D gmem/smem vs 2.5D shapes) and print its JSON")
     ap.add_argument("--cpml-only", action="store_true",
@@ -383,6 +444,12 @@ def main():
         sys.exit(2)
     if args.study_only:
         print(json.dumps({"kernel_study_1024": kernel_study_leg()}), flush=True)
+        return
+    if args.serving_only:
+        out = {"small_shot_probe": small_shot_probe()}
+        if args.serving > 0:
+            out["serving"] = serving_leg(args.serving, args.serving_lanes, args.serving_slots)
+        print(json.dumps(out), flush=True)
         return
     dev = torch.device("cuda:0")
     W = workload("large")
@@ -472,7 +539,8 @@ def main():
         out["gradient_256"] = gradient_leg()
         print(f"[bench] gradient: {out['gradient_256']}", file=sys.stderr, flush=True)
     if args.serving > 0:
-        out["serving"] = serving_leg(args.serving)
+        out["small_shot_probe"] = small_shot_probe()
+        out["serving"] = serving_leg(args.serving, args.serving_lanes, args.serving_slots)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W, vel)

@@ -29,10 +29,11 @@ def _requests():
     return out
 
 
-def test_each_shot_is_the_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("lanes", [0, 2])
+def test_each_shot_is_the_same_alone_and_in_the_mix(lanes):
     reqs = _requests()
-    print("case: 10 shots mixed, 4 slots, graph chunks", flush=True)
-    server = ShotServer(GpuBackend(graph_steps=10), budget_bytes=4 << 30, max_slots=4, chunk_steps=40)
+    print(f"case: 10 shots mixed, 4 slots, graph chunks, lanes {lanes}", flush=True)
+    server = ShotServer(GpuBackend(graph_steps=10, lanes=lanes), budget_bytes=4 << 30, max_slots=4, chunk_steps=40)
     mixed = server.run(reqs)
     summary = summarize(mixed, reqs, server.elapsed)
     print(summary, "max concurrent", server.max_concurrent, flush=True)

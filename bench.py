@@ -35,7 +35,7 @@ BYTES_PER_POINT = {"f32": 16, "f16": 12, "bf16": 12}
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("wave_kernels.hip", "wave_internal.h"):
+    for name in ("step_kernels.h", "step_f32.hip", "wave_internal.h"):
         with open(os.path.join(ROOT, "paper_2404_04441_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -77,32 +77,92 @@ def cpu_baseline(W, vel):
                       f"FP64 NumPy oracle, single thread, {t:.1f} s; host reports {os.cpu_count()} CPUs"}
 
 
-def stream_ceiling(dev, n: int) -> dict:
-    """What plain streams of the step's size reach on this GPU: a device copy
-    (1 read + 1 write) and torch.addcmul d = a + b * c (3 reads + 1 write, the
-    step's traffic pattern), both over n float32 elements."""
+_PROBE = None
+
+
+def _probe_lib():
+    """The hand-written stream kernels (libwave_probe.so, built with libwave)."""
+    global _PROBE
+    if _PROBE is None:
+        import ctypes
+
+        path = os.path.join(ROOT, "paper_2404_04441_amd", "libwave_probe.so")
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} missing: build with python -m paper_2404_04441_amd.build")
+        L = ctypes.CDLL(path)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        L.probe_stream_3r1w.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.probe_copy.argtypes = [vp, vp, sz, vp]
+        _PROBE = L
+    return _PROBE
+
+
+def stream_ceiling(dev, n: int, reps: int = 20) -> dict:
+    """What plain streams of the step's size reach on this GPU: hand-written
+    HIP kernels over n float32 elements, with the step kernel's access
+    policies (16-B lanes, nontemporal loads of the read-once arrays and
+    nontemporal stores, XCD-remapped workgroups): d = a + b * c (3 reads + 1
+    write, the float32 step's traffic shape) and a copy (1 read + 1 write)."""
     import torch
 
+    n = n // 4 * 4
+    lib = _probe_lib()
     a = torch.ones(n, dtype=torch.float32, device=dev)
     b = torch.ones_like(a)
     c = torch.ones_like(a)
     d = torch.empty_like(a)
-    out = {}
-    for name, fn, nbytes in (("copy", lambda: d.copy_(a), 8 * n),
-                             ("addcmul_3r1w", lambda: torch.addcmul(a, b, c, out=d), 16 * n)):
+    st = torch.cuda.current_stream(dev)
+    out = {"kernel": "libwave_probe stream_3r1w / copy_1r1w", "elements": n}
+    for name, fn, nbytes in (
+            ("stream_3r1w", lambda: lib.probe_stream_3r1w(a.data_ptr(), b.data_ptr(), c.data_ptr(), d.data_ptr(), n,
+                                                          st.cuda_stream), 16 * n),
+            ("copy", lambda: lib.probe_copy(a.data_ptr(), d.data_ptr(), n, st.cuda_stream), 8 * n)):
         for _ in range(3):
-            fn()
+            assert fn() == 0
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(20):
+        e0.record(st)
+        for _ in range(reps):
             fn()
-        e1.record()
+        e1.record(st)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 20
+        ms = e0.elapsed_time(e1) / reps
+        out[f"{name}_ms"] = round(ms, 4)
         out[f"{name}_gb_per_s"] = round(nbytes / ms / 1e6, 1)
+    assert torch.equal(d[:4], a[:4])  # the copy ran
     del a, b, c, d
     torch.cuda.empty_cache()
+    return out
+
+
+def size_probe(n: int, steps: int = 30) -> dict:
+    """One grid size N^3 (smooth random model, Dirichlet, a line of
+    receivers): the HIP stream ceiling of that size, then the float32 step
+    kernel in its tuned configuration; its algorithmic GB/s (16 B per point)
+    against the ceiling.  Run under rocprofv3 counters, it gives the bytes
+    each kernel moves per launch."""
+    import torch
+
+    from paper_2404_04441_amd import Solver
+    from synth import workload
+    from synth.velocity import smooth_random_torch
+    from synth.workloads import line_receivers
+
+    dev = torch.device("cuda:0")
+    W = workload("precision")
+    out = {"grid": f"{n}^3", "ceiling": stream_ceiling(dev, n ** 3)}
+    v = smooth_random_torch((n, n, n), seed=3, device=dev)
+    rec = line_receivers(n, n // 2, 4)
+    wav = torch.from_numpy(W.wavelet(steps)).to(dev)
+    tr = torch.empty((steps, len(rec)), dtype=torch.float32, device=dev)
+    s = Solver(v, W.h, W.dt, src=(n // 2, n // 2, n // 2), rec=rec)
+    s.run(3, wav, tr)
+    r = kernel_rate(s, steps, wav, tr, n ** 3, BYTES_PER_POINT["f32"])
+    r["tiling"] = s.tiling()
+    s.close()
+    r["frac_of_stream_3r1w"] = round(r["gb_per_s"] / out["ceiling"]["stream_3r1w_gb_per_s"], 4)
+    out["step_f32"] = r
+    print(f"[bench] size probe {n}^3: {out}", file=sys.stderr, flush=True)
     return out
 
 
@@ -213,7 +273,7 @@ def precision_leg(nt: int = 500) -> dict:
         print(f"[bench] precision 1024^3 {fmt}: {out[fmt]}", file=sys.stderr, flush=True)
     del vel
     torch.cuda.empty_cache()
-    out["stream_ceiling"] = stream_ceiling(dev, W.npts)  # plain torch streams of the 1024^3 size
+    out["stream_ceiling"] = stream_ceiling(dev, W.npts)  # HIP streams of the 1024^3 size
     return out
 
 
@@ -426,6 +486,8 @@ def main():
                     help="run only the 1024^3 kernel study (3D gmem/smem vs 2.5D shapes) and print its JSON")
     ap.add_argument("--cpml-only", action="store_true",
                     help="run only the 512^3 CPML leg (fused and unfused shapes) and print its JSON")
+    ap.add_argument("--size-probe", type=int, default=0,
+                    help="run only the N^3 size probe (HIP stream ceiling + tuned float32 step) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -444,6 +506,11 @@ def main():
         sys.exit(2)
     if args.study_only:
         print(json.dumps({"kernel_study_1024": kernel_study_leg()}), flush=True)
+        return
+    if args.size_probe:
+        if args.copy_calibration:
+            copy_calibration(torch.device("cuda:0"))
+        print(json.dumps({"size_probe": size_probe(args.size_probe)}), flush=True)
         return
     if args.serving_only:
         out = {"small_shot_probe": small_shot_probe()}

@@ -15,6 +15,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwave.so")
+# the benchmark's bandwidth ceilings (plain streams of the step's traffic
+# shape), a library of their own: not part of libwave's interface
+PROBE_LIB = os.path.join(PKG, "libwave_probe.so")
+PROBE_SOURCES = ["stream_probe.hip"]
 ARCH = "gfx950"
 
 # The step-kernel templates (step_kernels.h) are instantiated in one unit per
@@ -37,10 +41,10 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source for gfx950 and link libwave.so; returns its path."""
     cc = hipcc()
-    objs, cmds = [], []
+    objs, probe_objs, cmds = [], [], []
     build_dir = os.path.join(PKG, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    for src in SOURCES:
+    for src in SOURCES + PROBE_SOURCES:
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         cmd = [cc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
                "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -48,14 +52,15 @@ def build(verbose: bool = False) -> str:
             cmd[1:1] = ["-x", "hip"]
             cmd += DEVICE_FLAGS
         cmds.append(cmd)
-        objs.append(obj)
+        (probe_objs if src in PROBE_SOURCES else objs).append(obj)
     jobs = max(1, min(len(cmds), os.cpu_count() or 1, 16))
     with ThreadPoolExecutor(jobs) as pool:
         for f in [pool.submit(_run, c, verbose) for c in cmds]:
             f.result()
-    tmp = LIB + ".tmp"
-    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
-    os.replace(tmp, LIB)
+    for lib, parts in ((LIB, objs), (PROBE_LIB, probe_objs)):
+        tmp = lib + ".tmp"
+        _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + parts, verbose)
+        os.replace(tmp, lib)
     return LIB
 
 

@@ -303,7 +303,18 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   // wavefronts with nothing to write go there, so no write is predicated
   constexpr int LP = LH * LW + 64 * VEC;
   constexpr int DUMMY = LH * LW;
-  __shared__ __attribute__((aligned(16))) float lds[2][LP];
+  // LEADH: the x and y halo of A^n is loaded with the lead plane z+R, when
+  // the neighbouring tiles load the same lines as their own lead (so those
+  // loads meet in L2), instead of R planes later at the centre plane, by
+  // which time the lines have often left L2.  Planes z .. z+R then live in a
+  // ring of R+2 LDS planes: iteration z writes plane z+R into slot
+  // (z+R) mod 6 and reads plane z from slot z mod 6; the next iteration's
+  // writes go to the slot read one iteration earlier, so one barrier per
+  // plane still suffices.  Plain forward kernels whose ring fits 150 KB of
+  // LDS; the others stage the centre plane double-buffered.
+  constexpr bool LEADH = !ADJ && !CP && 6 * LP * 4 <= 150 * 1024;
+  constexpr int NSLOT = LEADH ? R + 2 : 2;
+  __shared__ __attribute__((aligned(16))) float lds[NSLOT][LP];
   __shared__ __attribute__((aligned(16))) float ldsF[ADJ ? 2 : 1][ADJ ? LP : 1];
   // CPML: psi_x rows of the tile (TY rows of LW, no y halo) and a scratch row
   constexpr int LPX = TY * LW + 64 * VEC;
@@ -512,8 +523,8 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       st.m[j] = ld_words<NF, NTP>(rM, vrow_f[j], scf);
     }
 #pragma unroll
-    for (int i = 0; i < NYH; ++i) st.yh[i] = ld_words<NA, 0>(rU, vyh[i], sc);
-    st.xh = ld_words<S == kF32 ? 4 : 2, 0>(rU, vxh, sc);
+    for (int i = 0; i < NYH; ++i) st.yh[i] = ld_words<NA, 0>(rU, vyh[i], LEADH ? sl : sc);
+    st.xh = ld_words<S == kF32 ? 4 : 2, 0>(rU, vxh, LEADH ? sl : sc);
     if constexpr (ADJ) {
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
@@ -572,6 +583,24 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) qF[k][j][i] = __uint_as_float(tf.w[i]);
       }
+    }
+  }
+  if constexpr (LEADH) {  // ring slots 0 .. R-1: planes zb .. zb+R-1 with their halo
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      float *Lk = lds[k];
+      const uint32_t s0 = so(zb + k);
+#pragma unroll
+      for (int j = 0; j < RY; ++j) lds_put<VEC>(Lk + (R + w * RY + j) * LW + R + VEC * lane, q[R + k][j]);
+#pragma unroll
+      for (int i = 0; i < NYH; ++i) {
+        const Words<NA> t = ld_words<NA, 0>(rU, vyh[i], s0);
+        float v[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[e] = row_get<S>(t, e) * inv_cur;
+        lds_put<VEC>(Lk + yhlds[i], v);
+      }
+      Lk[xhlds] = row_get<S>(ld_words<S == kF32 ? 4 : 2, 0>(rU, vxh, s0), 0) * inv_cur;
     }
   }
   // semi-stencil partials: slot (p - zb + R) mod 9 holds sum_m kz_m A(p-m) of plane p
@@ -677,13 +706,16 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       constexpr int cslot = (s + R) % kQ;  // plane z
       StageT &cs = stg[s % PD];
       const int par = (z - zb) & 1;
-      float *L = lds[par];
+      // L: the centre plane z (read after the barrier); Lw: the plane staged
+      // in this iteration (plane z+R with LEADH, else plane z)
+      float *L = lds[LEADH ? (z - zb) % NSLOT : par];
+      float *Lw = LEADH ? lds[(z - zb + R) % NSLOT] : L;
       float *LF = ldsF[ADJ ? par : 0];
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) q[(s + 2 * R) % kQ][j][i] = row_get<S>(cs.lead[j], i) * inv_cur;
-        lds_put<VEC>(L + (R + w * RY + j) * LW + R + VEC * lane, q[cslot][j]);
+        lds_put<VEC>(Lw + (R + w * RY + j) * LW + R + VEC * lane, q[LEADH ? (s + 2 * R) % kQ : cslot][j]);
         if constexpr (SEMI) {  // left half of plane z+R from planes z .. z+R-1
 #pragma unroll
           for (int i = 0; i < VEC; ++i) {
@@ -705,14 +737,14 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
         float t[VEC];
 #pragma unroll
         for (int i = 0; i < VEC; ++i) t[i] = row_get<S>(cs.yh[k], i) * inv_cur;
-        lds_put<VEC>(L + yhlds[k], t);
+        lds_put<VEC>(Lw + yhlds[k], t);
         if constexpr (ADJ) {
 #pragma unroll
           for (int i = 0; i < VEC; ++i) t[i] = __uint_as_float(cs.yhF[k].w[i]);
           lds_put<VEC>(LF + yhlds[k], t);
         }
       }
-      L[xhlds] = row_get<S>(cs.xh, 0) * inv_cur;
+      Lw[xhlds] = row_get<S>(cs.xh, 0) * inv_cur;
       if constexpr (ADJ) LF[xhlds] = cs.xhF;
       float *LX = ldsX[CP ? par : 0];
       float zex[CP ? RY : 1][CP ? VEC : 1];

@@ -29,8 +29,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 # algorithmic bytes per point-step: float32 reads A^n, A^{n-1}, m and writes A^{n+1};
-# 16-bit storage reads A^n, V^n (2 B each) and m, writes A^{n+1} and V^{n+1}
-BYTES_PER_POINT = {"f32": 16, "f16": 12, "bf16": 12}
+# 16-bit storage reads A^n, V^n (2 B each) and m (4 B, or 2 B as 16-bit codes),
+# writes A^{n+1} and V^{n+1}
+BYTES_PER_POINT = {"f32": 16, "f16": 12, "bf16": 12, "f16_m16": 10, "bf16_m16": 10}
+# the survey's figure for a 16-bit storage step (two 16-bit levels read, one
+# written, float32 m): each 16-bit form is also quoted against it
+SURVEY_16BIT_BYTES = 10
 
 
 def kernel_source_hash() -> str:
@@ -182,8 +186,10 @@ def copy_calibration(dev) -> None:
     torch.cuda.empty_cache()
 
 
-def kernel_rate(s, nt, wav, traces, npts, bpp):
-    """Average step-kernel time (events on the solver's stream) -> Gpts/s, GB/s."""
+def kernel_rate(s, nt, wav, traces, npts, bpp, ref_bpp=None):
+    """Average step-kernel time (events on the solver's stream) -> Gpts/s, GB/s
+    and the fraction of 8 TB/s at bpp algorithmic bytes per point (and at
+    ref_bpp, if given)."""
     import torch
 
     e0 = torch.cuda.Event(enable_timing=True)
@@ -194,8 +200,17 @@ def kernel_rate(s, nt, wav, traces, npts, bpp):
     e1.record(s.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / nt
-    return {"kernel_ms": round(ms, 4), "gpts_per_s": round(npts / ms / 1e6, 2),
-            "gb_per_s": round(bpp * npts / ms / 1e6, 1), "roofline_frac": round(bpp * npts / ms / 1e6 / PEAK_HBM_GBS, 4)}
+    out = {"kernel_ms": round(ms, 4), "gpts_per_s": round(npts / ms / 1e6, 2), "bytes_per_point": bpp,
+           "gb_per_s": round(bpp * npts / ms / 1e6, 1), "roofline_frac": round(bpp * npts / ms / 1e6 / PEAK_HBM_GBS, 4)}
+    if ref_bpp:
+        out[f"roofline_frac_at_{ref_bpp}B"] = round(ref_bpp * npts / ms / 1e6 / PEAK_HBM_GBS, 4)
+    return out
+
+
+def _storage_kw(form):
+    """Solver arguments of a storage form: "f16", "bf16_m16", ..."""
+    fmt, _, m = form.partition("_")
+    return {"storage": fmt, "model_bits": 16 if m == "m16" else 32}
 
 
 def storage_forms_leg(W, vel_dev, nt: int) -> dict:
@@ -207,11 +222,11 @@ def storage_forms_leg(W, vel_dev, nt: int) -> dict:
     out = {}
     wav = torch.from_numpy(W.wavelet(nt)).to(vel_dev.device)
     traces = torch.empty((nt, len(W.rec)), dtype=torch.float32, device=vel_dev.device)
-    for fmt in ("f16", "bf16"):
+    for fmt in ("f16", "bf16", "f16_m16", "bf16_m16"):
         s = Solver(vel_dev, W.h, W.dt, src=W.src, rec=W.rec, sponge_width=W.sponge_width,
-                   sponge_alpha=W.sponge_alpha, storage=fmt)
+                   sponge_alpha=W.sponge_alpha, **_storage_kw(fmt))
         s.run(20, wav, traces)
-        out[fmt] = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT[fmt])
+        out[fmt] = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT[fmt], SURVEY_16BIT_BYTES)
         s.close()
     return out
 
@@ -265,10 +280,11 @@ def precision_leg(nt: int = 500) -> dict:
     wav = torch.from_numpy(W.wavelet(nt)).to(dev)
     traces = torch.empty((nt, len(W.rec)), dtype=torch.float32, device=dev)
     out = {"workload": f"{W.name}, {nt} steps, Dirichlet, line of 1024 receivers"}
-    for fmt in ("f32", "f16", "bf16"):
-        s = Solver(vel, W.h, W.dt, src=W.src, rec=W.rec, storage=fmt)
+    for fmt in ("f32", "f16", "bf16", "f16_m16", "bf16_m16"):
+        s = Solver(vel, W.h, W.dt, src=W.src, rec=W.rec, **_storage_kw(fmt))
         s.run(10, wav, traces)
-        out[fmt] = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT[fmt])
+        out[fmt] = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT[fmt],
+                               None if fmt == "f32" else SURVEY_16BIT_BYTES)
         s.close()
         print(f"[bench] precision 1024^3 {fmt}: {out[fmt]}", file=sys.stderr, flush=True)
     del vel

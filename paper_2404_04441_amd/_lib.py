@@ -49,6 +49,7 @@ class WaveParams(ctypes.Structure):
         ("cpml_reflection", ctypes.c_double),
         ("cpml_f0", ctypes.c_double),
         ("cache_hint", ctypes.c_int32),
+        ("model_bits", ctypes.c_int32),
     ]
 
 

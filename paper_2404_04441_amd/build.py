@@ -23,8 +23,8 @@ ARCH = "gfx950"
 
 # The step-kernel templates (step_kernels.h) are instantiated in one unit per
 # storage type and one for the adjoint, so the units compile in parallel.
-SOURCES = ["step_f32.hip", "step_f16.hip", "step_bf16.hip", "step_adj.hip", "wave_kernels.hip", "wave_static.hip",
-           "wave_runtime.cpp"]
+SOURCES = ["step_f32.hip", "step_f16.hip", "step_bf16.hip", "step_f16m.hip", "step_bf16m.hip", "step_adj.hip",
+           "wave_kernels.hip", "wave_static.hip", "wave_runtime.cpp"]
 
 # Packed-FP32 instructions stay off: they are not used on purpose anywhere in
 # the kernels, and the compiler would otherwise form them from float pairs.

@@ -82,11 +82,19 @@ template <> struct Codec<kF32> {
   __device__ static raw enc(float x) { return x; }
 };
 
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 b16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+
 template <> struct Codec<kF16> {
   using raw = uint16_t;
   __device__ static float dec(raw r) { return static_cast<float>(__builtin_bit_cast(_Float16, r)); }
   __device__ static raw enc(float x) {  // round to nearest even (v_cvt_f16_f32)
     return __builtin_bit_cast(uint16_t, static_cast<_Float16>(x));
+  }
+  // two values, low half first: one v_cvt_pk_f16_f32 (round to nearest even)
+  __device__ static uint32_t enc2(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2v{lo, hi}), h16x2));
   }
 };
 
@@ -95,6 +103,9 @@ template <> struct Codec<kBF16> {
   __device__ static float dec(raw r) { return __uint_as_float(static_cast<uint32_t>(r) << 16); }
   __device__ static raw enc(float x) {  // round to nearest even: gfx950's v_cvt_pk_bf16_f32
     return __builtin_bit_cast(uint16_t, static_cast<__bf16>(x));
+  }
+  __device__ static uint32_t enc2(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2v{lo, hi}), b16x2));
   }
 };
 
@@ -181,11 +192,11 @@ __device__ __forceinline__ Words<VEC * (S == kF32 ? 4 : 2)> row_put(const float 
   if constexpr (S == kF32) {
 #pragma unroll
     for (int i = 0; i < VEC; ++i) r.w[i] = __float_as_uint(v[i]);
+  } else if constexpr (VEC == 1) {
+    r.w[0] = Codec<S>::enc(v[0]);
   } else {
 #pragma unroll
-    for (int k = 0; k < r.N; ++k) r.w[k] = 0u;
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) r.w[i >> 1] |= static_cast<uint32_t>(Codec<S>::enc(v[i])) << (16 * (i & 1));
+    for (int k = 0; k < VEC / 2; ++k) r.w[k] = Codec<S>::enc2(v[2 * k], v[2 * k + 1]);
   }
   return r;
 }
@@ -229,13 +240,14 @@ __device__ __forceinline__ int slab_index(int i, int n, int W) {
 // vector-memory load of the z loop lives here: s_waitcnt vmcnt retires loads
 // in issue order, so a load consumed in the same iteration would also wait for
 // every prefetch issued before it.
-template <int S, int RY, int VEC, int NYH, bool ADJ, bool CP>
+template <int S, int RY, int VEC, int NYH, bool ADJ, bool CP, bool M16 = false>
 struct Stage {
   static constexpr int NA = VEC * (S == kF32 ? 4 : 2);  // bytes of one A-type row
   static constexpr int NF = VEC * 4;                    // bytes of one float row
+  static constexpr int NM = VEC * (M16 ? 2 : 4);        // bytes of one row of m (or of its codes)
   Words<NA> lead[RY];             // A^n at plane z+R (enters the z queue)
   Words<NA> p[RY];                // A^{n-1} (or V^n) at plane z
-  Words<NF> m[RY];                // m at plane z
+  Words<NM> m[RY];                // m (or its 16-bit codes) at plane z
   Words<NA> yh[NYH];              // y-halo rows of A^n at plane z owned by this wavefront
   Words<S == kF32 ? 4 : 2> xh;    // x-halo value of A^n at plane z (lanes < 8*RY)
   float gz;                       // sponge factor of plane z
@@ -281,9 +293,11 @@ static_assert(kPadZ >= (kQ - 1) + kMaxPD + R, "z padding must cover the last tri
 // nontemporal one, so that a grid whose fields fit the last-level cache stays
 // there from step to step (forward; chosen by create-time tuning or the
 // caller).
-template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ, bool CP, bool KEEP>
+// M16: m is read as 16-bit codes (m = m_lo + u m_step; 16-bit storage only).
+template <int S, int BY, int RY, int PD, int VEC, bool SEMI, bool ADJ, bool CP, bool KEEP, bool M16 = false>
 __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
-  using StageT = Stage<S, RY, VEC, (2 * R + BY - 1) / BY, ADJ, CP>;
+  using StageT = Stage<S, RY, VEC, (2 * R + BY - 1) / BY, ADJ, CP, M16>;
+  static_assert(!M16 || (S != kF32 && !ADJ && !CP && !SEMI), "16-bit model codes: 16-bit storage forward");
   constexpr int NA = StageT::NA, NF = StageT::NF;
   constexpr int TX = kTileX * VEC;
   constexpr int TY = BY * RY;
@@ -394,7 +408,8 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   const rsrc_t rP = make_rsrc(P + base_b, span);
   const rsrc_t rO = make_rsrc(O + base_b, span);
   const rsrc_t rVo = make_rsrc((S != kF32 ? static_cast<char *>(a.vout) : O) + base_b, span);
-  const rsrc_t rM = make_rsrc(a.m + base, span_f);
+  const rsrc_t rM = M16 ? make_rsrc(reinterpret_cast<const char *>(a.m) + base * 2, span)
+                        : make_rsrc(a.m + base, span_f);
   const rsrc_t rnull = make_rsrc(a.gz, 0u);
   const rsrc_t rF = make_rsrc((ADJ ? a.fwd : a.m) + base, span_f);
   const rsrc_t rI = make_rsrc((ADJ ? a.img : a.m) + base, ADJ ? span_f : 0u);
@@ -520,7 +535,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
     for (int j = 0; j < RY; ++j) {
       st.lead[j] = ld_words<NA, 0>(rU, vrow[j], sl);
       st.p[j] = ld_words<NA, NTP>(rP, vrow[j], sc);
-      st.m[j] = ld_words<NF, NTP>(rM, vrow_f[j], scf);
+      st.m[j] = ld_words<StageT::NM, NTP>(rM, M16 ? vrow[j] : vrow_f[j], M16 ? sc : scf);
     }
 #pragma unroll
     for (int i = 0; i < NYH; ++i) st.yh[i] = ld_words<NA, 0>(rU, vyh[i], LEADH ? sl : sc);
@@ -763,7 +778,12 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
           pc[j][i] = row_get<S>(cs.p[j], i) * inv_prev;
-          mc[j][i] = __uint_as_float(cs.m[j].w[i]);
+          if constexpr (M16) {
+            const uint32_t u = (cs.m[j].w[i >> 1] >> (16 * (i & 1))) & 0xffffu;
+            mc[j][i] = fmaf(static_cast<float>(u), a.m_step, a.m_lo);
+          } else {
+            mc[j][i] = __uint_as_float(cs.m[j].w[i]);
+          }
           ic[j][i] = ADJ ? __uint_as_float(cs.img[ADJ ? j : 0].w[i]) : 0.f;
           rc[j][i] = ADJ ? cs.res[ADJ ? j : 0][ADJ ? i : 0] : 0.f;
         }
@@ -1115,10 +1135,22 @@ int blocks_variant(int v, bool cpml) {
   }
 }
 
-template <int FAM, int S, int BY, int RY, int PD, int VEC, bool ADJ>
+template <int FAM, int S, int BY, int RY, int PD, int VEC, bool ADJ, bool M16 = false>
 hipError_t launch_one(const StepArgs &a, hipStream_t s) {
   const unsigned grid = static_cast<unsigned>((a.total_tiles + 7) / 8 * 8);
-  if constexpr (FAM == 0) {
+  if constexpr (M16) {  // 16-bit storage forward with 16-bit model codes
+    if constexpr (FAM != 0 || S == kF32 || ADJ) {
+      return hipErrorInvalidValue;
+    } else {
+      if (a.keep)
+        hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, false, false, true, true>), dim3(grid),
+                           dim3(64 * BY), 0, s, a);
+      else
+        hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, false, false, false, true>), dim3(grid),
+                           dim3(64 * BY), 0, s, a);
+      return hipGetLastError();
+    }
+  } else if constexpr (FAM == 0) {
     if constexpr (S == kF32 && !ADJ && fuses_cpml<RY, VEC>()) {
       if (a.cpml) {
         hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, false, false, true, false>), dim3(grid), dim3(64 * BY),
@@ -1148,11 +1180,11 @@ hipError_t launch_one(const StepArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int S, bool ADJ>
+template <int S, bool ADJ, bool M16 = false>
 hipError_t launch_variant(int v, const StepArgs &a, hipStream_t s) {
   switch (v) {
 #define WAVE_VARIANT_CASE(id, fam, by, ry, pd, vec) \
-  case id: return launch_one<fam, S, by, ry, pd, vec, ADJ>(a, s);
+  case id: return launch_one<fam, S, by, ry, pd, vec, ADJ, M16>(a, s);
     WAVE_VARIANTS(WAVE_VARIANT_CASE)
 #undef WAVE_VARIANT_CASE
     default: return hipErrorInvalidValue;
@@ -1167,6 +1199,8 @@ hipError_t launch_variant_f32(int v, const StepArgs &a, hipStream_t s);
 hipError_t launch_variant_f16(int v, const StepArgs &a, hipStream_t s);
 hipError_t launch_variant_bf16(int v, const StepArgs &a, hipStream_t s);
 hipError_t launch_variant_adj(int v, const StepArgs &a, hipStream_t s);
+hipError_t launch_variant_f16m(int v, const StepArgs &a, hipStream_t s);   // 16-bit model codes
+hipError_t launch_variant_bf16m(int v, const StepArgs &a, hipStream_t s);
 int blocks_variant_f32(int v, bool cpml);
 int blocks_variant_f16(int v);
 int blocks_variant_bf16(int v);

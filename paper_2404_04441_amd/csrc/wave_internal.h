@@ -105,6 +105,9 @@ struct StepArgs {
   // 1: the fields read or written once with the regular cache policy
   // (forward 2.5D, no CPML), for grids whose fields fit the last-level cache
   int keep;
+  // 16-bit storage only: m holds 16-bit codes u, m = m_lo + u * m_step
+  int m16;
+  float m_lo, m_step;
 };
 
 struct Variant {
@@ -127,7 +130,11 @@ int step_blocks_per_cu(int storage, int variant, bool cpml);
 
 // Launchers; each returns the hipError_t of the launch.
 hipError_t launch_step(int storage, int variant, bool adjoint, const StepArgs &a, hipStream_t s);
+// m = (v dt)^2 (skipped when m is null) and the velocity range / validity into st
 hipError_t launch_init_m(const float *vel, float *m, size_t n, float dt, StepState *st, hipStream_t s);
+// codes u = round(((v dt)^2 - m_lo) / m_step), clamped to [0, 65535] (0 when m_step == 0)
+hipError_t launch_encode_m16(const float *vel, uint16_t *codes, size_t n, float dt, float m_lo, float m_step,
+                             hipStream_t s);
 hipError_t launch_bump(StepState *st, int count, hipStream_t s);
 hipError_t launch_decode(int storage, const void *field, float *out, size_t n, const StepState *st,
                          int slot_from_n_offset, bool v_field, hipStream_t s);

@@ -332,7 +332,7 @@ __global__ void init_m_kernel(const float *__restrict__ vel, float *__restrict__
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
     const float v = vel[i];
     const float t = v * dt;
-    m[i] = t * t;
+    if (m) m[i] = t * t;
     if (!(v > 0.f) || !(v < __builtin_huge_valf())) bad = 1;
     lo = fminf(lo, v);
     hi = fmaxf(hi, v);
@@ -358,6 +358,16 @@ __global__ void init_m_kernel(const float *__restrict__ vel, float *__restrict__
     if (bad) atomicOr(&st->flags, 2u);
     if (lo > 0.f) atomicMin(&st->vmin_bits, __float_as_uint(lo));
     atomicMax(&st->vmax_bits, __float_as_uint(fmaxf(hi, 0.f)));
+  }
+}
+
+__global__ void encode_m16_kernel(const float *__restrict__ vel, uint16_t *__restrict__ codes, size_t n, float dt,
+                                  float m_lo, float m_step) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const float t = vel[i] * dt;
+    const float u = m_step > 0.f ? rintf((t * t - m_lo) / m_step) : 0.f;
+    codes[i] = static_cast<uint16_t>(fminf(fmaxf(u, 0.f), 65535.f));
   }
 }
 
@@ -503,14 +513,20 @@ hipError_t launch_step(int storage, int variant, bool adjoint, const StepArgs &a
   }
   switch (storage) {
     case kF32: return launch_variant_f32(variant, a, s);
-    case kF16: return launch_variant_f16(variant, a, s);
-    case kBF16: return launch_variant_bf16(variant, a, s);
+    case kF16: return a.m16 ? launch_variant_f16m(variant, a, s) : launch_variant_f16(variant, a, s);
+    case kBF16: return a.m16 ? launch_variant_bf16m(variant, a, s) : launch_variant_bf16(variant, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_init_m(const float *vel, float *m, size_t n, float dt, StepState *st, hipStream_t s) {
   hipLaunchKernelGGL(init_m_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, vel, m, n, dt, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_m16(const float *vel, uint16_t *codes, size_t n, float dt, float m_lo, float m_step,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(encode_m16_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, vel, codes, n, dt, m_lo, m_step);
   return hipGetLastError();
 }
 

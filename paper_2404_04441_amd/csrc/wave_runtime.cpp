@@ -85,6 +85,9 @@ int validate(const wave_params *p) {
   if (p->tune < 0 || p->tune > 1) return WAVE_EINVAL;
   // the cached policy exists for the 2.5D forward kernels without CPML
   if (p->cache_hint < 0 || p->cache_hint > 1) return WAVE_EINVAL;
+  // 16-bit model codes exist for the 16-bit storage forward step only
+  if (p->model_bits != 0 && p->model_bits != 32 && p->model_bits != 16) return WAVE_EINVAL;
+  if (p->model_bits == 16 && p->storage == WAVE_F32) return WAVE_EINVAL;
   if (p->cache_hint == 1 && (p->cpml_width > 0 || (p->variant > 0 && variant_info(p->variant).family != 0)))
     return WAVE_EINVAL;
   return WAVE_OK;
@@ -115,7 +118,7 @@ int plan(const wave_params *p, Layout *L) {
   L->rec_off = take(4 * (static_cast<size_t>(p->nrec) + 1));
   L->rec_ord = take(4 * static_cast<size_t>(p->nrec));
   L->grec = take(4 * static_cast<size_t>(p->nrec));
-  L->m = take(4 * Np);
+  L->m = take((p->model_bits == 16 ? 2 : 4) * Np);  // m: float32, or 16-bit codes
   L->fa = take(es * Np);
   L->fb = take(es * Np);
   // 16-bit storage keeps V^n = A^n - g A^{n-1} besides the A ping-pong pair
@@ -278,6 +281,8 @@ struct wave_ctx {
   int n = 0;      // host mirror of the step counter
   Coef c{};
   float src_scale = 0.f, gamma = 0.f;
+  bool m16 = false;                  // m held as 16-bit codes: m = m_lo + u * m_step
+  float m_lo = 0.f, m_step = 0.f;
   RecBox box{};
   bool fused_rec = false;
   Tiling fwd{}, adj{};  // forward and adjoint step kernels
@@ -326,6 +331,9 @@ StepArgs base_args(const wave_ctx *w, const Tiling &t) {
   a.st = w->st;
   a.gamma = w->gamma;
   a.nrec = w->p.nrec;
+  a.m16 = w->m16 ? 1 : 0;
+  a.m_lo = w->m_lo;
+  a.m_step = w->m_step;
   return a;
 }
 
@@ -445,7 +453,7 @@ int do_reset(wave_ctx *w) {
 // steps on the zeroed fields and keep the fastest.  All candidates compute
 // identical bits, so the choice only changes speed.
 struct TuneEntry {
-  int nx, ny, nz, storage, cache_hint;
+  int nx, ny, nz, storage, cache_hint, model_bits;
   bool cpml, adjoint;
   Tiling t;
 };
@@ -458,7 +466,7 @@ int tune_forward(wave_ctx *w) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     for (const TuneEntry &e : g_tune_cache)
       if (e.nx == p.nx && e.ny == p.ny && e.nz == p.nz && e.storage == p.storage && e.cpml == w->cpml &&
-          e.cache_hint == p.cache_hint && e.adjoint == (p.adjoint != 0)) {
+          e.cache_hint == p.cache_hint && e.adjoint == (p.adjoint != 0) && e.model_bits == (p.model_bits == 16)) {
         w->fwd = e.t;
         w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
         return WAVE_OK;
@@ -551,7 +559,8 @@ int tune_forward(wave_ctx *w) {
   if (e1) (void)hipEventDestroy(e1);
   if (!rc) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune_cache.push_back(TuneEntry{p.nx, p.ny, p.nz, p.storage, p.cache_hint, w->cpml, p.adjoint != 0, best});
+    g_tune_cache.push_back(
+        TuneEntry{p.nx, p.ny, p.nz, p.storage, p.cache_hint, p.model_bits == 16, w->cpml, p.adjoint != 0, best});
   }
   return rc;
 }
@@ -737,8 +746,12 @@ int create_ctx(const wave_params *p, const float *vel_dev, void *ws_dev, size_t 
     if (!rc) rc = hip_rc(hipMemcpyAsync(w->rec_ord, ord.data(), 4 * ord.size(), hipMemcpyHostToDevice, w->stream));
     if (!rc) rc = hip_rc(hipMemcpyAsync(w->grec, grec.data(), 4 * grec.size(), hipMemcpyHostToDevice, w->stream));
   }
-  if (!rc) rc = hip_rc(launch_init_m(vel_dev, w->m, w->N, static_cast<float>(p->dt), w->st, w->stream));
-  if (!rc) rc = hip_rc(launch_fill_zero(w->m + w->N, 4 * (w->Np - w->N), w->stream));
+  w->m16 = p->model_bits == 16;
+  // float32 m is written by the range pass itself; 16-bit codes need the
+  // range first (encoded below, once it is known on the host)
+  if (!rc) rc = hip_rc(launch_init_m(vel_dev, w->m16 ? nullptr : w->m, w->N, static_cast<float>(p->dt), w->st,
+                                     w->stream));
+  if (!rc && !w->m16) rc = hip_rc(launch_fill_zero(w->m + w->N, 4 * (w->Np - w->N), w->stream));
   if (!rc) rc = hip_rc(hipMemcpyAsync(&back, w->st, sizeof(back), hipMemcpyDeviceToHost, w->stream));
   if (!rc) rc = hip_rc(hipStreamSynchronize(w->stream));
   if (!rc && (back.flags & 2u)) rc = WAVE_EINVAL;  // non-finite or non-positive velocity
@@ -753,6 +766,16 @@ int create_ctx(const wave_params *p, const float *vel_dev, void *ws_dev, size_t 
     for (int m = 1; m <= 4; ++m) kabs += 2.0 * std::fabs(kC[m]) * (ix2 + iy2 + iz2);
     const double k0 = kC[0] * (ix2 + iy2 + iz2);
     w->gamma = static_cast<float>(Mmax * (std::fabs(k0) + kabs));
+    if (!rc && w->m16) {  // codes of m = (v dt)^2 over [m_lo, m_hi] of this grid
+      float vmin;
+      std::memcpy(&vmin, &back.vmin_bits, 4);
+      const float tlo = vmin * static_cast<float>(p->dt), thi = vmax * static_cast<float>(p->dt);
+      w->m_lo = tlo * tlo;  // the float32 m of the extreme nodes, as the float32 path computes it
+      w->m_step = (thi * thi - w->m_lo) / 65535.f;
+      uint16_t *codes = reinterpret_cast<uint16_t *>(w->m);
+      rc = hip_rc(launch_encode_m16(vel_dev, codes, w->N, static_cast<float>(p->dt), w->m_lo, w->m_step, w->stream));
+      if (!rc) rc = hip_rc(launch_fill_zero(codes + w->N, 2 * (w->Np - w->N), w->stream));
+    }
     if (!rc && p->cpml_width > 0) rc = setup_cpml(w, vmax);
     w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
   }

@@ -221,3 +221,25 @@ def test_static_workspace_size_checked_before_the_device(lib):
     assert lib.wave_create_static(ctypes.byref(p), fake_vel, None, ctypes.byref(h)) == L.WAVE_EINVAL
     assert lib.wave_create_static(None, fake_vel, None, ctypes.byref(h)) == L.WAVE_EINVAL
     assert not h.value
+
+
+def test_model_bits_validation(lib):
+    """16-bit model codes exist for 16-bit wavefield storage only."""
+    p = L.WaveParams()
+    lib.wave_params_init(ctypes.byref(p))
+    p.nx = p.ny = p.nz = 16
+    p.dt = 1e-4
+    b = ctypes.c_size_t()
+    ws32 = ctypes.c_size_t()
+    assert lib.wave_workspace_bytes(ctypes.byref(p), ctypes.byref(ws32)) == L.WAVE_OK
+    p.model_bits = 16
+    assert lib.wave_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == L.WAVE_EINVAL  # float32 storage
+    p.storage = L.WAVE_F16
+    p.model_bits = 8
+    assert lib.wave_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == L.WAVE_EINVAL
+    p.model_bits = 32
+    assert lib.wave_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == L.WAVE_OK
+    full = b.value
+    p.model_bits = 16
+    assert lib.wave_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == L.WAVE_OK
+    assert b.value < full  # m as 2-byte codes

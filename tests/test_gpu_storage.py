@@ -86,6 +86,48 @@ def test_storage_matches_emulated_scheme(fmt):
     assert e_plain <= BOUND_PLAIN[fmt]
 
 
+def _model16_velocity(vel, dt):
+    """The velocity whose m the step reads with model_bits = 16: the header's
+    affine code of m = (v dt)^2 between the grid's extreme m, rounded to
+    nearest, evaluated in float32 as the library evaluates it (m = (v dt)^2,
+    u = rint((m - m_lo) / step), m' = m_lo + u step, each in float32).  The
+    16-bit schemes are chaotic in their rounding decisions: moving m by one
+    code step at some nodes (1e-5) moves the bf16 emulation by 5e-3, the
+    size of its own storage error, so the emulation must see the same codes."""
+    f = np.float32
+    t = vel.astype(f) * f(dt)
+    m = t * t
+    tlo, thi = f(vel.min()) * f(dt), f(vel.max()) * f(dt)
+    lo = tlo * tlo
+    step = (thi * thi - lo) / f(65535)
+    u = np.clip(np.rint((m - lo) / step), 0, 65535) if step > 0 else np.zeros_like(m)
+    mq = (u.astype(np.float64) * float(step) + float(lo)).astype(f)  # one rounding, as the fused multiply-add
+    return np.sqrt(mq.astype(np.float64)) / dt
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_model16_matches_emulated_scheme(fmt):
+    """16-bit model codes: the GPU against the oracle's emulation of the same
+    storage scheme run on the velocity the codes represent (same bound as
+    with float32 m: the decode adds float32 roundings only)."""
+    shape, h, vel, dt, nt, wav, rec, src, plain = ragged()
+    _say(f"case: {fmt} storage with 16-bit model codes, ragged {shape}, {nt} steps")
+    vq = _model16_velocity(vel, dt)
+    dm = np.abs(vq ** 2 / vel.astype(np.float64) ** 2 - 1).max()
+    emu = forward_stored(vq, h, dt, src, wav, rec, nt, fmt, sponge_width=5, sponge_alpha=0.05)
+    got = gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05, storage=fmt, model_bits=16)
+    e_emu = oracle.rel_l2(got["u"], emu["u"])
+    e_emu_tr = oracle.rel_l2(got["traces"], emu["traces"])
+    e_plain = oracle.rel_l2(got["u"], plain["u"])
+    _say(f"{fmt} m16: max relative change of m {dm:.2e}; gpu-vs-emulation u={e_emu:.3e} traces={e_emu_tr:.3e}; "
+         f"gpu-vs-fp64 {e_plain:.3e}")
+    vmin, vmax = float(vel.min()), float(vel.max())
+    assert dm <= (vmax ** 2 / vmin ** 2 - 1) / 131070 * 1.001  # half a code step, float32 evaluation
+    assert got["flags"] == 0
+    assert e_emu <= TOL_EMUL[fmt] and e_emu_tr <= TOL_EMUL[fmt]
+    assert e_plain <= BOUND_PLAIN[fmt]
+
+
 def _stencil_terms(A, h):
     """sum_a sum_m |c_m| / h_a^2 (|A(+m) - A| + |A(-m) - A|) at every node:
     the size of the terms a float32 evaluation of the Laplacian sums."""
@@ -184,12 +226,13 @@ def test_precision_crop_16bit_error_report():
     W = workload("precision_crop")
     ref = crop_reference("float64")
     for fmt in ("f16", "bf16"):
-        got = gpu_run(W.velocity(), W.h, W.dt, W.src, W.wavelet(), W.rec, W.nt, storage=fmt)
-        e_u = oracle.rel_l2(got["u"], ref["u"])
-        e_t = oracle.rel_l2(got["traces"], ref["traces"])
-        _say(f"crop {fmt}: rel-L2 field {e_u:.3e} traces {e_t:.3e}")
-        assert got["flags"] == 0
-        assert e_u <= BOUND_PLAIN[fmt]
+        for bits in (32, 16):
+            got = gpu_run(W.velocity(), W.h, W.dt, W.src, W.wavelet(), W.rec, W.nt, storage=fmt, model_bits=bits)
+            e_u = oracle.rel_l2(got["u"], ref["u"])
+            e_t = oracle.rel_l2(got["traces"], ref["traces"])
+            _say(f"crop {fmt} (m in {bits} bits): rel-L2 field {e_u:.3e} traces {e_t:.3e}")
+            assert got["flags"] == 0
+            assert e_u <= BOUND_PLAIN[fmt]
 
 
 def test_precision_crop_float32_within_1e5():

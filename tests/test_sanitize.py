@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2404_04441_amd", "csrc")
 # every kernel object the library is linked from (the .hip units of the build)
 KOBJS = [os.path.join(ROOT, "paper_2404_04441_amd", "_build", n) for n in
-         ("step_f32.o", "step_f16.o", "step_bf16.o", "step_adj.o", "wave_kernels.o")]
+         ("step_f32.o", "step_f16.o", "step_bf16.o", "step_f16m.o", "step_bf16m.o", "step_adj.o", "wave_kernels.o")]
 ROCM = "/opt/rocm"
 
 

@@ -123,6 +123,15 @@ typedef struct {
                                 relative error in m of at most (m_max / m_min - 1) / 131070 (6.1e-5
                                 for a 1500..4500 m/s model), and a step that moves 10 instead of 12
                                 bytes per node (2 + 2 + 2 read, 2 + 2 written) */
+  int32_t time_block;        /* 2: advance two time steps per pass over the grid (temporal blocking,
+                                the multi-step blocking of paper Sec. II's related work): the pass
+                                kernel (variant family 4) computes step n+1 on 64 x 32 tiles and
+                                step n+2 on their 56 x 24 interiors, R planes behind along z; A^k is
+                                kept in buffer k mod 4 (two more float32 fields in the workspace).
+                                Same bits as one step per pass.  Float32 forward only: needs no
+                                CPML, no adjoint, cache_hint 0, variant 0 or family 4 and
+                                graph_steps a multiple of 4; tune is not applied.  An odd step count
+                                ends with a single step.  0 (default): one step per pass */
 } wave_params;
 
 /* Fill `p` with defaults: no source, no receivers, float32 storage,
@@ -268,7 +277,8 @@ int wave_variant_count(void);
  * storage and forward steps only; they compute the same bits as family 0.
  * Family 3 is the 2.5D blocking with the z sum as a semi-stencil (the
  * paper's st_semi, same section): float32 forward only, the z sum in another
- * order (not bitwise equal to family 0).  Errors: WAVE_EINVAL for a null
+ * order (not bitwise equal to family 0).  Family 4 is the two-steps-per-pass
+ * kernel of time_block = 2 (by, ry give its 64 x by*ry first-step tile).  Errors: WAVE_EINVAL for a null
  * `info` or an out-of-range variant. */
 int wave_variant_info(int32_t variant, int32_t *info);
 

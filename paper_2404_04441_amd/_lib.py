@@ -50,6 +50,7 @@ class WaveParams(ctypes.Structure):
         ("cpml_f0", ctypes.c_double),
         ("cache_hint", ctypes.c_int32),
         ("model_bits", ctypes.c_int32),
+        ("time_block", ctypes.c_int32),
     ]
 
 

@@ -1065,12 +1065,279 @@ __global__ void __launch_bounds__(64 * BY * BZ) smem_kernel(StepArgs a) {
 }
 
 
+// ------------------------------------------------------------ two time steps per pass
+//
+// Temporal blocking (the multi-step blocking the paper cites among related
+// work in Sec. II): one pass over the grid advances two time steps.  A
+// workgroup of 8 wavefronts covers a 64 x 32 region E (a lane per column, 4
+// rows per wavefront); it computes step n+1 on all of E and step n+2 on E's
+// interior O (56 x 24: E less a ring of R = 4 nodes), R planes behind in z.
+// The ring's step n+1 is also computed by the neighbouring workgroups: the
+// price of keeping step n+2's stencil inside the workgroup.  Per plane z:
+//   * step n+1 at plane z on E: A^n from a register queue (z) and a
+//     double-buffered LDS plane (x and y, with E's halo), A^{n-1} and m
+//     from the prefetch stage;
+//   * A^{n+1}(z) enters a second register queue and a ring of R+1 LDS
+//     planes (E only), and m(z) a third queue;
+//   * step n+2 at plane z-R on O: A^{n+1} from that queue and ring, A^n at
+//     plane z-R (the oldest slot of the first queue) as its previous level.
+// Both steps perform step_kernel's operations in its order (the Laplacian
+// as centred second differences), so a pass gives the bits of two single
+// steps.  The two results go to two further buffers: writing in place would
+// race with neighbouring workgroups that still read the ring's inputs.
+// Float32 forward without CPML.  A z-chunk of output planes [zb, ze) runs
+// step n+1 over [zb-R, ze+R): 2R extra planes per chunk.
+constexpr int kTbBY = 8, kTbRY = 4;                        // E: 64 x 32
+constexpr int kTbEX = kTileX, kTbEY = kTbBY * kTbRY;
+constexpr int kTbOX = kTbEX - 2 * R, kTbOY = kTbEY - 2 * R;  // O: 56 x 24
+
+__global__ void __launch_bounds__(64 * kTbBY) step2_kernel(StepArgs a) {
+  constexpr int BY = kTbBY, RY = kTbRY, EX = kTbEX, EY = kTbEY;
+  constexpr int LW = EX + 2 * R, LH = EY + 2 * R;
+  constexpr int DUMMY = LH * LW;  // scratch row for halo lanes with nothing to write
+  static_assert(2 * R <= BY && 8 * RY <= 64, "one y-halo row per wavefront, x halo in one load");
+  __shared__ __attribute__((aligned(16))) float ldsA[2][LH * LW + 64];
+  __shared__ __attribute__((aligned(16))) float ldsB[R + 1][EY * EX];
+
+  const int nwg = static_cast<int>(gridDim.x);
+  const int bid = static_cast<int>(blockIdx.x);
+  const int logical = (bid & 7) * (nwg >> 3) + (bid >> 3);
+  if (logical >= a.total_tiles) return;
+  const int tix = logical % a.tiles_x;
+  const int rest = logical / a.tiles_x;
+  const int tiy = rest % a.tiles_y;
+  const int chunk = rest / a.tiles_y;
+  const int ex0 = tix * kTbOX - R, ey0 = tiy * kTbOY - R;  // corner of E
+  const int zb = chunk * a.zchunk;
+  const int zend = min(zb + a.zchunk, a.nz);  // output planes [zb, zend)
+  const int z1b = zb - R;                      // step n+1 planes [z1b, z1e), whole trips of nine
+  const int z1e = z1b + (zend - zb + 2 * R + kQ - 1) / kQ * kQ;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const uint32_t pbytes = static_cast<uint32_t>(nx) * static_cast<uint32_t>(ny) * 4u;
+  const int n = a.st->n + a.k;  // this pass advances steps n and n+1
+
+  // Resources over the planes [zlo, zhi) the pass touches, cut at the end of
+  // the padded allocation (loads past it read zero); planes below zlo are
+  // below the grid and read zero through rnull.
+  const int zlo = max(z1b - R, 0);
+  const int zhi = min(z1e + R + 1, nz + kPadZ);
+  const uint32_t span = zhi > zlo ? static_cast<uint32_t>(zhi - zlo) * pbytes : 0u;
+  const size_t base = static_cast<size_t>(zlo) * static_cast<size_t>(nx) * static_cast<size_t>(ny);
+  const rsrc_t rU = make_rsrc(static_cast<const float *>(a.cur) + base, span);
+  const rsrc_t rP = make_rsrc(static_cast<const float *>(a.prev) + base, span);
+  const rsrc_t rM = make_rsrc(a.m + base, span);
+  const rsrc_t rO = make_rsrc(static_cast<float *>(a.out) + base, span);
+  const rsrc_t rO2 = make_rsrc(static_cast<float *>(a.out2) + base, span);
+  const rsrc_t rnull = make_rsrc(a.gz, 0u);
+  const rsrc_t rgz = make_rsrc(a.gz, static_cast<uint32_t>(nz + kPadZ) * 4u);
+  const rsrc_t rrz = make_rsrc(a.rz, static_cast<uint32_t>(nz + kPadZ) * 4u);
+  auto ld = [&](const rsrc_t &r, uint32_t voff, int z, int aux) {  // float of plane z (zero below zlo)
+    const bool ok = z >= zlo;
+    const rsrc_t rr = ok ? r : rnull;
+    const uint32_t so = ok ? static_cast<uint32_t>(z - zlo) * pbytes : 0u;
+    return aux ? __uint_as_float(ld_words<4, kNT>(rr, voff, so).w[0]) : __uint_as_float(ld_words<4, 0>(rr, voff, so).w[0]);
+  };
+  auto tab = [&](const rsrc_t &r, int z) {  // per-plane table entry (0 below the grid)
+    return ld_words<4, 0>(z >= 0 ? r : rnull, 0u, z >= 0 ? static_cast<uint32_t>(z) * 4u : 0u).w[0];
+  };
+
+  // ---- this lane's column and rows
+  const int ex = ex0 + lane;
+  const bool xin = ex >= 0 && ex < nx;
+  const float gxv = xin ? a.gx[ex] : 0.f;
+  const bool ocol = lane >= R && lane < EX - R && xin;
+  int rxi = -1;
+  if (a.box.cnx > 0 && ocol) {
+    const int d = ex - a.box.x0;
+    if (d >= 0 && d % a.box.sx == 0 && d / a.box.sx < a.box.cnx) rxi = d / a.box.sx;
+  }
+  float gyv[RY], qrow[RY];
+  int ryi[RY];
+  bool orow[RY];
+  uint32_t vrow[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    const int er = w * RY + j, ey = ey0 + er;
+    const bool yin = ey >= 0 && ey < ny;
+    vrow[j] = (xin && yin) ? (static_cast<uint32_t>(ey) * static_cast<uint32_t>(nx) + static_cast<uint32_t>(ex)) * 4u
+                           : kOOB;
+    gyv[j] = yin ? a.gy[ey] : 0.f;
+    orow[j] = er >= R && er < EY - R && yin;
+    ryi[j] = -1;
+    if (a.box.cnx > 0 && yin) {
+      const int d = ey - a.box.y0;
+      if (d >= 0 && d % a.box.sy == 0 && d / a.box.sy < a.box.cny) ryi[j] = d / a.box.sy;
+    }
+    qrow[j] = (a.sx >= 0 && a.sx == ex && a.sy == ey) ? 1.f : 0.f;
+  }
+  // y halo of E: wavefront w loads halo row w (rows above E first)
+  const int hr = w < R ? w : EY + w;
+  const int hy = ey0 - R + hr;
+  const int yhlds = hr * LW + R + lane;
+  const uint32_t vyh =
+      (xin && hy >= 0 && hy < ny) ? (static_cast<uint32_t>(hy) * static_cast<uint32_t>(nx) + static_cast<uint32_t>(ex)) * 4u
+                                  : kOOB;
+  // x halo of E: lane l < 8 RY covers row l/8 of this wavefront, column l%8
+  int xhlds = DUMMY + lane;
+  uint32_t vxh = kOOB;
+  if (lane < 8 * RY) {
+    const int j = lane >> 3, c = lane & 7;
+    const int gxx = c < R ? ex0 - R + c : ex0 + EX + (c - R);
+    const int yj = ey0 + w * RY + j;
+    xhlds = (R + w * RY + j) * LW + (c < R ? c : EX + c);
+    if (gxx >= 0 && gxx < nx && yj >= 0 && yj < ny)
+      vxh = (static_cast<uint32_t>(yj) * static_cast<uint32_t>(nx) + static_cast<uint32_t>(gxx)) * 4u;
+  }
+
+  struct Stg {
+    float lead[RY], p[RY], m[RY], yh, xh, gz1, gz2;
+    int rz1, rz2;
+  };
+  auto load_stage = [&](Stg &st, int z) {  // plane z of step n+1 (and z-R of step n+2)
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      st.lead[j] = ld(rU, vrow[j], z + R, 0);
+      st.p[j] = ld(rP, vrow[j], z, 1);
+      st.m[j] = ld(rM, vrow[j], z, 1);
+    }
+    st.yh = ld(rU, vyh, z, 0);
+    st.xh = ld(rU, vxh, z, 0);
+    st.gz1 = __uint_as_float(tab(rgz, z));
+    st.gz2 = __uint_as_float(tab(rgz, z - R));
+    st.rz1 = static_cast<int>(tab(rrz, z));
+    st.rz2 = static_cast<int>(tab(rrz, z - R));
+  };
+
+  // queues: qa slot (p - z1b + R) mod 9 holds A^n of plane p; qb and qm slot
+  // (p - z1b) mod 9 hold A^{n+1} and m of plane p
+  float qa[kQ][RY], qb[kQ][RY], qm[kQ][RY];
+#pragma unroll
+  for (int k = 0; k < kQ; ++k)
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      qb[k][j] = 0.f;
+      qm[k][j] = 0.f;
+      qa[k][j] = k < 2 * R ? ld(rU, vrow[j], z1b - R + k, 0) : 0.f;
+    }
+  Stg stg;
+  load_stage(stg, z1b);
+  const float wsrc1 = a.sx >= 0 ? a.wavelet[n] * a.src_scale : 0.f;
+  const float wsrc2 = a.sx >= 0 ? a.wavelet[n + 1] * a.src_scale : 0.f;
+
+  for (int zs = z1b; zs < z1e; zs += kQ) {
+    static_for<kQ>([&](auto sc) __attribute__((always_inline)) {
+      constexpr int s = decltype(sc)::value;
+      const int z = zs + s;                 // step n+1 plane
+      const int z2 = z - R;                 // step n+2 plane
+      constexpr int ca = (s + R) % kQ;      // qa: plane z
+      constexpr int cb = (s + kQ - R) % kQ; // qb, qm: plane z - R
+      float *LA = ldsA[(z - z1b) & 1];
+      float *LB = ldsB[(z - z1b) % (R + 1)];
+      const float *LB2 = ldsB[(z2 - z1b + R + 1) % (R + 1)];
+#pragma unroll
+      for (int j = 0; j < RY; ++j) {
+        qa[(s + 2 * R) % kQ][j] = stg.lead[j];
+        LA[(R + w * RY + j) * LW + R + lane] = qa[ca][j];
+      }
+      LA[yhlds] = stg.yh;
+      LA[xhlds] = stg.xh;
+      float pc[RY], mc[RY];
+#pragma unroll
+      for (int j = 0; j < RY; ++j) {
+        pc[j] = stg.p[j];
+        mc[j] = stg.m[j];
+      }
+      const float gz1 = stg.gz1, gz2 = stg.gz2;
+      const int rz1 = __builtin_amdgcn_readfirstlane(stg.rz1), rz2 = __builtin_amdgcn_readfirstlane(stg.rz2);
+      load_stage(stg, z + 1);
+      __syncthreads();
+
+      // step n+1 at plane z on E
+      float v1[RY];
+#pragma unroll
+      for (int j = 0; j < RY; ++j) {
+        const float *row = LA + (R + w * RY + j) * LW + R + lane;
+        const float c = qa[ca][j];
+        float lap = 0.f;
+#pragma unroll
+        for (int m = 1; m <= R; ++m) {
+          const float yp = (j + m < RY) ? qa[ca][(j + m) % RY] : row[m * LW];
+          const float ym = (j - m >= 0) ? qa[ca][(j - m + RY) % RY] : row[-m * LW];
+          const float sx = (row[m] - c) + (row[-m] - c);
+          const float sy = (yp - c) + (ym - c);
+          const float sz = (qa[(s + R + m) % kQ][j] - c) + (qa[(s + R - m + kQ) % kQ][j] - c);
+          lap = fmaf(a.c.kx[m - 1], sx, lap);
+          lap = fmaf(a.c.ky[m - 1], sy, lap);
+          lap = fmaf(a.c.kz[m - 1], sz, lap);
+        }
+        const float g = gxv * (gyv[j] * gz1);
+        float t = fmaf(-g, pc[j], 2.f * c);
+        t = fmaf(mc[j], lap, t);
+        t = fmaf(qrow[j], z == a.sz ? wsrc1 : 0.f, t);
+        v1[j] = t * g;
+        qb[s][j] = v1[j];
+        qm[s][j] = mc[j];
+        LB[(w * RY + j) * EX + lane] = v1[j];
+      }
+      const bool out1 = z >= zb && z < zend;
+      if (out1) {
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v1[j]), rO,
+                                                static_cast<int>((ocol && orow[j]) ? vrow[j] : kOOB),
+                                                static_cast<int>(static_cast<uint32_t>(z - zlo) * pbytes), kNT);
+        if (rz1 >= 0 && rxi >= 0) {
+#pragma unroll
+          for (int j = 0; j < RY; ++j)
+            if (orow[j] && ryi[j] >= 0)
+              a.traces[static_cast<size_t>(n) * a.nrec + (rz1 * a.box.cny + ryi[j]) * a.box.cnx + rxi] = v1[j];
+        }
+      }
+
+      // step n+2 at plane z - R on O (the ring's threads compute at the
+      // nearest O node and discard the result)
+      const int lc = min(max(lane, R), EX - R - 1);
+#pragma unroll
+      for (int j = 0; j < RY; ++j) {
+        const int er = min(max(w * RY + j, R), EY - R - 1);
+        const float *row = LB2 + er * EX + lc;
+        const float c = qb[cb][j];
+        float lap = 0.f;
+#pragma unroll
+        for (int m = 1; m <= R; ++m) {
+          const float sx = (row[m] - c) + (row[-m] - c);
+          const float sy = (row[m * EX] - c) + (row[-m * EX] - c);
+          const float sz = (qb[(cb + m) % kQ][j] - c) + (qb[(cb - m + kQ) % kQ][j] - c);
+          lap = fmaf(a.c.kx[m - 1], sx, lap);
+          lap = fmaf(a.c.ky[m - 1], sy, lap);
+          lap = fmaf(a.c.kz[m - 1], sz, lap);
+        }
+        const float g = gxv * (gyv[j] * gz2);
+        float t = fmaf(-g, qa[s][j], 2.f * c);  // qa slot s: A^n of plane z - R
+        t = fmaf(qm[cb][j], lap, t);
+        t = fmaf(qrow[j], z2 == a.sz ? wsrc2 : 0.f, t);
+        const float v2 = t * g;
+        if (z2 >= zb && z2 < zend) {
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v2), rO2,
+                                                static_cast<int>((ocol && orow[j]) ? vrow[j] : kOOB),
+                                                static_cast<int>(static_cast<uint32_t>(z2 - zlo) * pbytes), kNT);
+          if (rz2 >= 0 && rxi >= 0 && orow[j] && ryi[j] >= 0)
+            a.traces[static_cast<size_t>(n + 1) * a.nrec + (rz2 * a.box.cny + ryi[j]) * a.box.cnx + rxi] = v2;
+        }
+      }
+    });
+  }
+}
+
 // Kernel variants (FAMILY, BY, RY, PD, VEC).  Family 0 is the 2.5D streaming
 // step_kernel (tile 64*VEC x BY*RY, PD planes in flight).  Variant 0 asks the
 // runtime for its automatic choice; its row is the shape that choice falls
 // back to, which variant 18 requests explicitly.  Families 1 (gmem)
 // and 2 (smem) are the 3D-blocked kernels with blocks of 64 x BY x RY nodes;
-// family 3 is the 2.5D kernel with the semi-stencil z sum.
+// family 3 is the 2.5D kernel with the semi-stencil z sum; family 4 the
+// two-steps-per-pass kernel (step2_kernel; its shape is fixed).
 #define WAVE_VARIANTS(X)  \
   X(0, 0, 8, 4, 3, 1)     \
   X(1, 0, 4, 8, 1, 1)     \
@@ -1090,7 +1357,8 @@ __global__ void __launch_bounds__(64 * BY * BZ) smem_kernel(StepArgs a) {
   X(15, 2, 4, 4, 1, 1)    \
   X(16, 3, 8, 4, 3, 1)    \
   X(17, 3, 8, 1, 3, 4)    \
-  X(18, 0, 8, 4, 3, 1)
+  X(18, 0, 8, 4, 3, 1)     \
+  X(19, 4, 8, 4, 1, 1)
 
 #define WAVE_VARIANT_INFO(id, fam, by, ry, pd, vec) {by, ry, pd, vec, fam},
 constexpr Variant kVariants[] = {WAVE_VARIANTS(WAVE_VARIANT_INFO)};
@@ -1169,6 +1437,8 @@ hipError_t launch_one(const StepArgs &a, hipStream_t s) {
                        a);
   } else if constexpr (S != kF32 || ADJ) {
     return hipErrorInvalidValue;  // the study families are float32 forward only
+  } else if constexpr (FAM == 4) {
+    hipLaunchKernelGGL(step2_kernel, dim3(grid), dim3(64 * kTbBY), 0, s, a);
   } else if constexpr (FAM == 3) {
     hipLaunchKernelGGL((step_kernel<S, BY, RY, PD, VEC, true, false, false, false>), dim3(grid), dim3(64 * BY), 0, s,
                        a);

@@ -76,6 +76,7 @@ struct StepArgs {
   const void *cur;    // A^n (storage type)
   const void *prev;   // A^{n-1} (float32) or V^n (16-bit)
   void *out;          // A^{n+1}; may alias prev (float32)
+  void *out2;         // two-step pass: A^{n+2} (a fourth buffer)
   void *vout;         // 16-bit storage: V^{n+1} (same buffer as prev)
   const float *m;     // (v dt)^2
   const float *gx, *gy, *gz;
@@ -116,8 +117,9 @@ struct Variant {
   int pd;   // z-planes of loads in flight ahead of the plane being computed
   int vec;  // consecutive x nodes per lane (tile width = 64 * vec); needs nx % vec == 0
   int family;  // 0: 2.5D streaming; 1: 3D blocks from global memory; 2: 3D blocks via LDS;
-               // 3: 2.5D streaming with a semi-stencil z sum (families 1 and 2: blocks of
-               // 64 x by x ry nodes; families 1-3: float32 forward only)
+               // 3: 2.5D streaming with a semi-stencil z sum; 4: two time steps per
+               // pass (families 1 and 2: blocks of 64 x by x ry nodes; families 1-4:
+               // float32 forward only)
 };
 
 int variant_count();

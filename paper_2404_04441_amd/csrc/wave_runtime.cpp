@@ -28,7 +28,7 @@ constexpr double kD1[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct Layout {
-  size_t st, gx, gy, gz, rz, rec_lin, rec_node, rec_off, rec_ord, grec, m, fa, fb, fv, ckpt, seg, mua, mub, img;
+  size_t st, gx, gy, gz, rz, rec_lin, rec_node, rec_off, rec_ord, grec, m, fa, fb, fc, fd, fv, ckpt, seg, mua, mub, img;
   size_t cpml_ab, cpml_slab[3], total;  // CPML: a/b tables, psi+zeta slab pair per axis
   int K, nck;
 };
@@ -85,6 +85,15 @@ int validate(const wave_params *p) {
   if (p->tune < 0 || p->tune > 1) return WAVE_EINVAL;
   // the cached policy exists for the 2.5D forward kernels without CPML
   if (p->cache_hint < 0 || p->cache_hint > 1) return WAVE_EINVAL;
+  // two time steps per pass: float32 forward, no CPML, its own kernel (variant 0 or its family's)
+  if (p->time_block != 0 && p->time_block != 2) return WAVE_EINVAL;
+  if (p->time_block == 2) {
+    if (p->storage != WAVE_F32 || p->cpml_width > 0 || p->adjoint || p->cache_hint != 0) return WAVE_EINVAL;
+    if (p->variant > 0 && variant_info(p->variant).family != 4) return WAVE_EINVAL;
+    if (p->graph_steps % 4) return WAVE_EINVAL;  // replays start at the same buffer phase (n mod 4)
+  } else if (p->variant > 0 && variant_info(p->variant).family == 4) {
+    return WAVE_EINVAL;
+  }
   // 16-bit model codes exist for the 16-bit storage forward step only
   if (p->model_bits != 0 && p->model_bits != 32 && p->model_bits != 16) return WAVE_EINVAL;
   if (p->model_bits == 16 && p->storage == WAVE_F32) return WAVE_EINVAL;
@@ -123,6 +132,12 @@ int plan(const wave_params *p, Layout *L) {
   L->fb = take(es * Np);
   // 16-bit storage keeps V^n = A^n - g A^{n-1} besides the A ping-pong pair
   L->fv = p->storage == WAVE_F32 ? off : take(es * Np);
+  // two steps per pass: A^k in buffer k mod 4 (no pass writes a buffer it reads)
+  L->fc = L->fd = off;
+  if (p->time_block == 2) {
+    L->fc = take(es * Np);
+    L->fd = take(es * Np);
+  }
   L->K = 0;
   L->nck = 0;
   L->ckpt = L->seg = L->mua = L->mub = L->img = off;
@@ -211,12 +226,34 @@ int auto_variant(const wave_params *p) {
 // The adjoint kernel keeps two z queues: its default is a one-node-per-lane
 // shape that fits in registers (8 wavefronts x 4 rows, one plane in flight).
 constexpr int kAdjointVariant = 5;
+// The two-steps-per-pass kernel (variant family 4).
+constexpr int kPairVariant = 19;
 
 Tiling make_tiling(const wave_params *p, int variant) {
   const int nx = p->nx, ny = p->ny, nz = p->nz;
   Tiling t;
   t.variant = variant;
   const Variant v = variant_info(variant);
+  if (v.family == 4) {  // two steps per pass: 56 x 24 output tiles (64 x 32 for the first step)
+    t.tiles_x = (nx + kTileX - 2 * kRadius - 1) / (kTileX - 2 * kRadius);
+    t.tiles_y = (ny + v.by * v.ry - 2 * kRadius - 1) / (v.by * v.ry - 2 * kRadius);
+    // about one workgroup per CU (its LDS and registers allow one); each
+    // chunk also runs 2R planes of the first step beyond its outputs
+    const int per_plane = t.tiles_x * t.tiles_y;
+    int zc = p->zchunk;
+    if (zc <= 0) {
+      const int chunks = std::max(1, (256 + per_plane / 2) / per_plane);
+      zc = std::max(std::min(nz, 27), (nz + chunks - 1) / chunks);
+    }
+    // a workgroup's resources span its chunk plus 2R + 9 + R + 1 planes, below 2^31 bytes
+    const int64_t plane_f = 4 * static_cast<int64_t>(nx) * ny;
+    const int zc_max = static_cast<int>(((int64_t(1) << 31) - 1) / plane_f) - (3 * kRadius + 10);
+    zc = std::max(1, std::min(zc, zc_max));
+    t.zchunk = zc;
+    t.nchunks = (nz + zc - 1) / zc;
+    t.total_tiles = t.tiles_x * t.tiles_y * t.nchunks;
+    return t;
+  }
   if (v.family == 1 || v.family == 2) {  // 3D blocks of 64 x by x ry nodes
     t.tiles_x = (nx + kTileX - 1) / kTileX;
     t.tiles_y = (ny + v.by - 1) / v.by;
@@ -275,7 +312,7 @@ struct wave_ctx {
   int64_t *rec_node = nullptr;  // distinct receiver nodes, ascending (adjoint injection)
   int32_t *rec_off = nullptr, *rec_ord = nullptr;
   int nrec_nodes = 0;
-  void *fa = nullptr, *fb = nullptr, *fv = nullptr;
+  void *fa = nullptr, *fb = nullptr, *fc = nullptr, *fd = nullptr, *fv = nullptr;
   size_t N = 0;   // interior nodes
   size_t Np = 0;  // nodes of a padded field (interior + kPadZ zero planes)
   int n = 0;      // host mirror of the step counter
@@ -286,8 +323,9 @@ struct wave_ctx {
   RecBox box{};
   bool fused_rec = false;
   Tiling fwd{}, adj{};  // forward and adjoint step kernels
+  Tiling pair{};        // time_block == 2: the two-steps-per-pass kernel
   // graph replay cache: one graph per buffer parity
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};  // by buffer phase
   const float *g_wavelet = nullptr;
   float *g_traces = nullptr;
 
@@ -300,7 +338,14 @@ struct wave_ctx {
         g = nullptr;
       }
   }
-  void *field(int parity) const { return parity ? fb : fa; }  // A^k lives in field(k & 1)
+  // A^k lives in field(k): buffer k mod 2, or k mod 4 with two steps per pass
+  void *field(int k) const {
+    if (p.time_block == 2) {
+      void *const b[4] = {fa, fb, fc, fd};
+      return b[k & 3];
+    }
+    return (k & 1) ? fb : fa;
+  }
 };
 
 namespace {
@@ -352,11 +397,30 @@ int enqueue_steps(wave_ctx *w, int count, const float *wavelet, float *traces, b
     a.cp = w->cp;
   }
   if (sample && w->fused_rec && !fix_pass) a.box = w->box;
+  const bool gather = sample && (!w->fused_rec || fix_pass) && w->p.nrec > 0;
   for (int k = 0; k < count; ++k) {
-    const int parity = (w->n + k) & 1;
-    a.cur = w->field(parity);
-    a.out = w->field(parity ^ 1);
-    a.prev = w->p.storage == WAVE_F32 ? w->field(parity ^ 1) : w->fv;
+    const int nk = w->n + k;
+    if (w->p.time_block == 2 && count - k >= 2) {  // steps nk and nk+1 in one pass
+      StepArgs b = base_args(w, w->pair);
+      b.wavelet = wavelet;
+      b.traces = traces;
+      if (sample && w->fused_rec) b.box = w->box;
+      b.cur = w->field(nk);
+      b.prev = w->field(nk + 3);
+      b.out = w->field(nk + 1);
+      b.out2 = w->field(nk + 2);
+      b.k = k;
+      int rc = hip_rc(launch_step(WAVE_F32, w->pair.variant, false, b, w->stream));
+      for (int e = 0; e < 2 && !rc && gather; ++e)
+        rc = hip_rc(launch_gather(w->p.storage, w->field(nk + 1 + e), w->rec_lin, w->p.nrec, traces, w->st, k + e,
+                                  w->stream));
+      if (rc) return rc;
+      ++k;
+      continue;
+    }
+    a.cur = w->field(nk);
+    a.out = w->field(nk + 1);
+    a.prev = w->p.storage == WAVE_F32 ? w->field(nk + 3) : w->fv;
     a.vout = w->fv;
     a.k = k;
     int rc = 0;
@@ -366,7 +430,7 @@ int enqueue_steps(wave_ctx *w, int count, const float *wavelet, float *traces, b
       rc = hip_rc(launch_cpml_fix(w->cp, static_cast<const float *>(a.cur), w->m, static_cast<float *>(a.out),
                                   w->cpml_fused, w->stream));
     if (rc) return rc;
-    if (sample && (!w->fused_rec || fix_pass) && w->p.nrec > 0) {
+    if (gather) {
       rc = hip_rc(launch_gather(w->p.storage, a.out, w->rec_lin, w->p.nrec, traces, w->st, k, w->stream));
       if (rc) return rc;
     }
@@ -383,7 +447,7 @@ int replay_graph(wave_ctx *w, int reps, const float *wavelet, float *traces) {
     w->g_wavelet = wavelet;
     w->g_traces = traces;
   }
-  const int parity = w->n & 1;
+  const int parity = w->p.time_block == 2 ? (w->n & 3) : (w->n & 1);
   if (!w->graph[parity]) {
     hipStream_t cs;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return WAVE_EHIP;
@@ -443,6 +507,8 @@ int do_reset(wave_ctx *w) {
   for (int a = 0; a < 3 && w->cpml && !rc; ++a)
     rc = hip_rc(launch_fill_zero(w->ws + w->L.cpml_slab[a], slab_bytes(w, a), w->stream));
   if (!rc) rc = hip_rc(launch_fill_zero(w->fb, es * w->Np, w->stream));
+  if (!rc && w->fc) rc = hip_rc(launch_fill_zero(w->fc, es * w->Np, w->stream));
+  if (!rc && w->fd) rc = hip_rc(launch_fill_zero(w->fd, es * w->Np, w->stream));
   if (!rc && w->fv) rc = hip_rc(launch_fill_zero(w->fv, es * w->Np, w->stream));
   if (!rc) rc = hip_rc(launch_reset_state(w->st, w->stream));
   if (!rc) w->n = 0;
@@ -677,6 +743,10 @@ int create_ctx(const wave_params *p, const float *vel_dev, void *ws_dev, size_t 
   w->fa = w->ws + L.fa;
   w->fb = w->ws + L.fb;
   w->fv = p->storage == WAVE_F32 ? nullptr : w->ws + L.fv;
+  if (p->time_block == 2) {
+    w->fc = w->ws + L.fc;
+    w->fd = w->ws + L.fd;
+  }
   const int nx = p->nx, ny = p->ny, nz = p->nz;
   w->N = static_cast<size_t>(nx) * ny * nz;
   w->Np = static_cast<size_t>(nx) * ny * (static_cast<size_t>(nz) + kPadZ);
@@ -725,8 +795,9 @@ int create_ctx(const wave_params *p, const float *vel_dev, void *ws_dev, size_t 
 
   // tiling: the forward step and (for adjoint contexts) the adjoint step
   // each get a shape; variant 0 picks the measured-best ones
-  w->fwd = make_tiling(p, p->variant > 0 ? p->variant : auto_variant(p));
+  w->fwd = make_tiling(p, (p->variant > 0 && p->time_block == 0) ? p->variant : auto_variant(p));
   w->fwd.keep = p->cache_hint == 1;
+  if (p->time_block == 2) w->pair = make_tiling(p, kPairVariant);
   if (p->adjoint) w->adj = make_tiling(p, p->variant > 0 ? p->variant : kAdjointVariant);
 
   StepState init{};
@@ -779,7 +850,7 @@ int create_ctx(const wave_params *p, const float *vel_dev, void *ws_dev, size_t 
     if (!rc && p->cpml_width > 0) rc = setup_cpml(w, vmax);
     w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
   }
-  if (!rc && p->tune && p->variant == 0 && p->zchunk == 0) {
+  if (!rc && p->tune && p->variant == 0 && p->zchunk == 0 && p->time_block == 0) {
     rc = do_reset(w);  // zero fields (and CPML memory) for the timing runs
     if (!rc) rc = tune_forward(w);
   }
@@ -872,8 +943,8 @@ int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *re
     if (rc) break;
     w->n += K;
     float *ck = ckpt + 2 * static_cast<size_t>(j - 1) * w->N;
-    rc = hip_rc(hipMemcpyAsync(ck, w->field(w->n & 1), fb, hipMemcpyDeviceToDevice, w->stream));
-    if (!rc) rc = hip_rc(hipMemcpyAsync(ck + w->N, w->field((w->n & 1) ^ 1), fb, hipMemcpyDeviceToDevice, w->stream));
+    rc = hip_rc(hipMemcpyAsync(ck, w->field(w->n), fb, hipMemcpyDeviceToDevice, w->stream));
+    if (!rc) rc = hip_rc(hipMemcpyAsync(ck + w->N, w->field(w->n + 3), fb, hipMemcpyDeviceToDevice, w->stream));
   }
   // padded fields start zero (their padding planes stay zero)
   const size_t fbp = 4 * w->Np;
@@ -931,20 +1002,20 @@ int wave_read_field(wave_t w, int32_t which, float *out_dev) {
   if (!w || !out_dev || which < 0 || which > 2) return WAVE_EINVAL;
   const bool f32 = w->p.storage == WAVE_F32;
   if (which == 0)
-    return hip_rc(launch_decode(w->p.storage, w->field(w->n & 1), out_dev, w->N, w->st, 0, false, w->stream));
+    return hip_rc(launch_decode(w->p.storage, w->field(w->n), out_dev, w->N, w->st, 0, false, w->stream));
   if (which == 2) {
     if (f32) return WAVE_EINVAL;
     return hip_rc(launch_decode(w->p.storage, w->fv, out_dev, w->N, w->st, 0, true, w->stream));
   }
   if (f32)
-    return hip_rc(launch_decode(w->p.storage, w->field((w->n & 1) ^ 1), out_dev, w->N, w->st, 3, false, w->stream));
-  return hip_rc(launch_decode_prev(w->p.storage, w->field(w->n & 1), w->fv, out_dev, w->gx, w->gy, w->gz, w->p.nx,
+    return hip_rc(launch_decode(w->p.storage, w->field(w->n + 3), out_dev, w->N, w->st, 3, false, w->stream));
+  return hip_rc(launch_decode_prev(w->p.storage, w->field(w->n), w->fv, out_dev, w->gx, w->gy, w->gz, w->p.nx,
                                    w->p.ny, w->p.nz, w->st, w->stream));
 }
 
 int wave_write_field(wave_t w, int32_t which, const float *in_dev) {
   if (!w || !in_dev || which < 0 || which > 1 || w->p.storage != WAVE_F32) return WAVE_EINVAL;
-  void *dst = w->field(which == 0 ? (w->n & 1) : ((w->n & 1) ^ 1));
+  void *dst = w->field(which == 0 ? w->n : w->n + 3);
   return hip_rc(hipMemcpyAsync(dst, in_dev, 4 * w->N, hipMemcpyDeviceToDevice, w->stream));
 }
 
@@ -991,11 +1062,18 @@ int wave_save_state(wave_t w, void *dst_dev) {
   h.nz = w->p.nz;
   h.storage = w->p.storage;
   h.cpml_width = w->p.cpml_width;
+  h.pad[0] = w->p.time_block;
   char *d = static_cast<char *>(dst_dev);
   int rc = hip_rc(hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, w->stream));
   if (!rc) rc = hip_rc(hipMemcpyAsync(d + 256, w->st, sizeof(StepState), hipMemcpyDeviceToDevice, w->stream));
   size_t off = 512;
+  // the two stored levels: by buffer, or by role (A^n, A^{n-1}) when they
+  // rotate through four buffers
   void *fields[3] = {w->fa, w->fb, w->fv};
+  if (w->p.time_block == 2) {
+    fields[0] = w->field(w->n);
+    fields[1] = w->field(w->n + 3);
+  }
   const int nfields = w->p.storage == WAVE_F32 ? 2 : 3;
   for (int k = 0; k < nfields && !rc; ++k, off += align256(fb))
     rc = hip_rc(hipMemcpyAsync(d + off, fields[k], fb, hipMemcpyDeviceToDevice, w->stream));
@@ -1018,11 +1096,16 @@ int wave_load_state(wave_t w, const void *src_dev) {
   if (!rc) rc = hip_rc(hipStreamSynchronize(w->stream));
   if (rc) return rc;
   if (h.magic != kStateMagic || h.bytes != total || h.field_bytes != fb || h.slab_bytes != sb || h.nx != w->p.nx ||
-      h.ny != w->p.ny || h.nz != w->p.nz || h.storage != w->p.storage || h.cpml_width != w->p.cpml_width || h.n < 0)
+      h.ny != w->p.ny || h.nz != w->p.nz || h.storage != w->p.storage || h.cpml_width != w->p.cpml_width || h.n < 0 ||
+      h.pad[0] != w->p.time_block)
     return WAVE_EINVAL;
   rc = hip_rc(hipMemcpyAsync(w->st, src + 256, sizeof(StepState), hipMemcpyDeviceToDevice, w->stream));
   size_t off = 512;
   void *fields[3] = {w->fa, w->fb, w->fv};
+  if (w->p.time_block == 2) {
+    fields[0] = w->field(h.n);
+    fields[1] = w->field(h.n + 3);
+  }
   const int nfields = w->p.storage == WAVE_F32 ? 2 : 3;
   for (int k = 0; k < nfields && !rc; ++k, off += align256(fb))
     rc = hip_rc(hipMemcpyAsync(fields[k], src + off, fb, hipMemcpyDeviceToDevice, w->stream));
@@ -1044,7 +1127,7 @@ int wave_time_index(wave_t w, int32_t *n) {
 
 int wave_sync_status(wave_t w, uint32_t *flags) {
   if (!w || !flags) return WAVE_EINVAL;
-  int rc = hip_rc(launch_check_finite(w->p.storage, w->field(w->n & 1), w->N, w->st, w->stream));
+  int rc = hip_rc(launch_check_finite(w->p.storage, w->field(w->n), w->N, w->st, w->stream));
   StepState back{};
   if (!rc) rc = hip_rc(hipMemcpyAsync(&back, w->st, sizeof(back), hipMemcpyDeviceToHost, w->stream));
   if (!rc) rc = hip_rc(hipStreamSynchronize(w->stream));
@@ -1075,13 +1158,13 @@ int wave_tiling(wave_t w, int32_t *out) {
   if (!w || !out) return WAVE_EINVAL;
   // variant 0 (automatic) runs its fallback shape: report the explicit
   // variant with that shape
-  int v = w->fwd.variant;
+  int v = w->p.time_block == 2 ? w->pair.variant : w->fwd.variant;
   for (int k = 1; v == 0 && k < variant_count(); ++k) {
     const Variant a = variant_info(0), b = variant_info(k);
     if (a.family == b.family && a.by == b.by && a.ry == b.ry && a.pd == b.pd && a.vec == b.vec) v = k;
   }
   out[0] = v;
-  out[1] = w->fwd.zchunk;
+  out[1] = w->p.time_block == 2 ? w->pair.zchunk : w->fwd.zchunk;
   out[2] = w->fwd.keep ? 1 : 0;
   return WAVE_OK;
 }

@@ -41,13 +41,14 @@ class Solver:
                  cache); 0 = nontemporal (tune also times the cacheable policy)
     model_bits : 32 (default) = m = (v dt)^2 in float32; 16 = a 16-bit affine code of m (16-bit
                  storage only; relative error in m <= (m_max / m_min - 1) / 131070, 10 B per node-step)
+    time_block : 2 = two time steps per pass over the grid (float32 forward; same bits), 0 = one
     """
 
     def __init__(self, vel: torch.Tensor, h, dt: float, src=None, rec=None, sponge_width: int = 0,
                  sponge_alpha: float = 0.015, storage: str = "f32", adjoint: bool = False, nt_max: int = 0,
                  ckpt_interval: int = 0, variant: int = 0, zchunk: int = 0, graph_steps: int = 0, tune: bool = True,
                  cpml_width: int = 0, cpml_reflection: float = 1e-3, cpml_f0: float = 0.0, cache_hint: int = 0,
-                 model_bits: int = 32, stream=None):
+                 model_bits: int = 32, time_block: int = 0, stream=None):
         lib = L.lib()
         _dev_f32(vel, "vel")
         nz, ny, nx = vel.shape
@@ -71,6 +72,7 @@ class Solver:
         p.cpml_width, p.cpml_reflection, p.cpml_f0 = int(cpml_width), float(cpml_reflection), float(cpml_f0)
         p.cache_hint = int(cache_hint)
         p.model_bits = int(model_bits)
+        p.time_block = int(time_block)
         nbytes = ctypes.c_size_t()
         L.check(lib.wave_workspace_bytes(ctypes.byref(p), ctypes.byref(nbytes)), "wave_workspace_bytes")
         self.workspace_bytes = nbytes.value

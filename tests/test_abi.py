@@ -187,9 +187,16 @@ def test_variant_info_and_shape_validation(lib):
         assert lib.wave_variant_info(v, info) == 0
         fam, by, ry, pd, vec = list(info)
         families.add(fam)
-        assert fam in (0, 1, 2, 3) and by >= 1 and ry >= 1 and pd >= 1 and vec in (1, 2, 4)
+        assert fam in (0, 1, 2, 3, 4) and by >= 1 and ry >= 1 and pd >= 1 and vec in (1, 2, 4)
         if fam in (0, 3):
             assert 9 % pd == 0 and 8 * ry <= 64
+        if fam == 4:  # the two-steps-per-pass kernel: only with time_block = 2, float32 forward
+            assert _bytes(lib, _params(lib, variant=v, nx=16))[0] == L.WAVE_EINVAL
+            assert _bytes(lib, _params(lib, variant=v, nx=18, time_block=2))[0] == 0
+            assert _bytes(lib, _params(lib, variant=v, time_block=2, storage=L.WAVE_F16))[0] == L.WAVE_EINVAL
+            assert _bytes(lib, _params(lib, variant=v, time_block=2, adjoint=1, nt_max=10))[0] == L.WAVE_EINVAL
+            assert _bytes(lib, _params(lib, variant=v, time_block=2, graph_steps=6))[0] == L.WAVE_EINVAL
+            continue
         # nx = 16 accepts every lane width; nx = 18 (even, not a multiple of 4) rejects vec 4
         assert _bytes(lib, _params(lib, variant=v, nx=16))[0] == 0
         assert (_bytes(lib, _params(lib, variant=v, nx=18))[0] == 0) == (vec != 4)
@@ -197,7 +204,13 @@ def test_variant_info_and_shape_validation(lib):
         rc16 = _bytes(lib, _params(lib, variant=v, nx=16, storage=L.WAVE_F16))[0]
         rcadj = _bytes(lib, _params(lib, variant=v, nx=16, adjoint=1, nt_max=10))[0]
         assert (rc16 == 0) == (fam == 0) and (rcadj == 0) == (fam == 0)
-    assert families == {0, 1, 2, 3}
+        # a one-step shape with time_block = 2 is refused (variant 0, automatic, is not a shape)
+        assert (_bytes(lib, _params(lib, variant=v, nx=16, time_block=2))[0] == L.WAVE_EINVAL) == (v != 0)
+    assert families == {0, 1, 2, 3, 4}
+    # time_block = 2 adds two float32 fields to the workspace
+    one = _bytes(lib, _params(lib))
+    two = _bytes(lib, _params(lib, time_block=2))
+    assert one[0] == two[0] == 0 and two[1] > one[1]
     assert lib.wave_variant_info(n, info) == L.WAVE_EINVAL
     assert lib.wave_variant_info(-1, info) == L.WAVE_EINVAL
     assert lib.wave_variant_info(0, None) == L.WAVE_EINVAL

@@ -79,7 +79,7 @@ def test_cpml_shapes_and_replay():
     nfused = 0
     for v in range(1, variant_count()):
         info = variant_info(v)
-        if vel.shape[2] % info["vec"]:
+        if vel.shape[2] % info["vec"] or info["family"] == 4:  # family 4 (two steps per pass) has no CPML
             continue
         _say(f"case: CPML variant {v} {info} fused={_fused(info)}")
         got = _gpu(vel, h, dt, wav, rec, src, W, nt, variant=v)

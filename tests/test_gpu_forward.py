@@ -91,6 +91,76 @@ def test_ragged_grid_with_sponge_parity(rec_kind):
     assert e_u <= TOL_F32 and e_up <= TOL_F32 and e_tr <= TOL_F32
 
 
+@pytest.mark.parametrize("rec_kind", ["box", "list"])
+def test_two_steps_per_pass_is_bitwise_one_step_per_pass(rec_kind):
+    """time_block = 2 (one pass advances steps n and n+1; tiles of 64 x 32
+    for the first step, 56 x 24 for the second) against one step per pass in
+    the fixed rule's shape: traces, A^n and the stored A^{n-1} bitwise equal,
+    for an odd step count (the last step single) and an even one, for
+    z-chunks from 5 planes to the whole grid, and with graph replay."""
+    shape, h, vel, dt, nt, wav, rec, src, ref = ragged_case(rec_kind)
+    kw = dict(sponge_width=5, sponge_alpha=0.05)
+    for steps in (nt, nt - 1):
+        base = gpu_run(vel, h, dt, src, wav, rec, steps, tune=False, **kw)
+        for extra in (dict(), dict(zchunk=5), dict(zchunk=37), dict(graph_steps=8)):
+            _say(f"case: ragged {shape} receivers={rec_kind} steps={steps} two steps per pass {extra}")
+            got = gpu_run(vel, h, dt, src, wav, rec, steps, time_block=2, **kw, **extra)
+            for key in ("u", "u_prev", "traces"):
+                assert np.array_equal(got[key], base[key]), (key, extra)
+    e_u = oracle.rel_l2(gpu_run(vel, h, dt, src, wav, rec, nt, time_block=2, **kw)["u"], ref["u"])
+    _say(f"two steps per pass vs FP64 oracle: rel-L2 u={e_u:.3e}")
+    assert e_u <= TOL_F32
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 13), (30, 26, 57), (9, 100, 64)])
+def test_two_steps_per_pass_small_and_edge_grids(shape):
+    """Grids smaller than one tile, fewer planes than the z reach, one tile
+    wide with many in y: still the bits of one step per pass."""
+    nz, ny, nx = shape
+    vel = smooth_random(shape, seed=nx + ny + nz)
+    dt = COURANT * 10.0 / 4500.0
+    wav = ricker(33, dt, 30.0)
+    src = (nx // 2, ny // 2, nz // 2)
+    rec = line_receivers(nx, ny // 2, min(2, nz - 1))
+    _say(f"case: two steps per pass on {shape}")
+    base = gpu_run(vel, 10.0, dt, src, wav, rec, 33, tune=False)
+    got = gpu_run(vel, 10.0, dt, src, wav, rec, 33, time_block=2)
+    assert np.abs(base["u"]).max() > 0
+    for key in ("u", "u_prev", "traces"):
+        assert np.array_equal(got[key], base[key]), key
+
+
+def test_two_steps_per_pass_small_workload_and_snapshot():
+    """The 64^3 workload with two steps per pass: the oracle at the float32
+    tolerance, and a snapshot taken after an odd step count (the buffers'
+    phase mod 4 is 3) resumes bit for bit in a second context."""
+    from paper_2404_04441_amd import Solver
+
+    W, vel, wav, ref = small_case()
+    _say("case: small 64^3, 200 steps, two steps per pass")
+    got = gpu_run(vel, W.h, W.dt, W.src, wav, W.rec, W.nt, time_block=2)
+    e_u = oracle.rel_l2(got["u"], ref["u"])
+    _say(f"rel-L2 u={e_u:.3e}")
+    assert e_u <= TOL_F32
+    v = torch.from_numpy(vel).cuda()
+    w = torch.from_numpy(wav).cuda()
+    a = Solver(v, W.h, W.dt, src=W.src, rec=W.rec, time_block=2)
+    tr_a = torch.zeros((W.nt, len(W.rec)), device="cuda")
+    a.reset()
+    a.step(71, w, tr_a)
+    snap = a.save_state()
+    a.step(W.nt - 71, w, tr_a)
+    b = Solver(v, W.h, W.dt, src=W.src, rec=W.rec, time_block=2)
+    tr_b = tr_a.clone()
+    tr_b[71:] = 0
+    b.load_state(snap)
+    b.step(W.nt - 71, w, tr_b)
+    assert torch.equal(a.read_field(0), b.read_field(0)) and torch.equal(a.read_field(1), b.read_field(1))
+    assert torch.equal(tr_a, tr_b)
+    a.close()
+    b.close()
+
+
 def test_tiling_variants_and_zchunks_are_bitwise_identical():
     """Every tile shape and z-chunk length runs the same arithmetic per node,
     so results must agree to the bit; an LDS race or halo bug breaks this."""
@@ -111,7 +181,9 @@ def test_tiling_variants_and_zchunks_are_bitwise_identical():
                     gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05, variant=v, zchunk=zc)
                 assert e.value.status == WAVE_EINVAL
                 continue
-            got = gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05, variant=v, zchunk=zc)
+            extra = dict(time_block=2) if info["family"] == 4 else {}  # the two-steps-per-pass kernel
+            got = gpu_run(vel, h, dt, src, wav, rec, nt, sponge_width=5, sponge_alpha=0.05, variant=v, zchunk=zc,
+                          **extra)
             if info["family"] == 3:
                 assert oracle.rel_l2(got["u"], ref["u"]) <= TOL_F32, (v, zc)
                 assert oracle.rel_l2(got["traces"], ref["traces"]) <= TOL_F32, (v, zc)
@@ -127,7 +199,9 @@ def test_tiling_variants_and_zchunks_are_bitwise_identical():
     for v in range(variant_count()):
         for zc in (0, 16):
             _say(f"case: nx=68 variant={v} zchunk={zc}")
-            got = gpu_run(vel2, h, dt, src, wav, rec2, nt, sponge_width=5, sponge_alpha=0.05, variant=v, zchunk=zc)
+            extra = dict(time_block=2) if variant_info(v)["family"] == 4 else {}
+            got = gpu_run(vel2, h, dt, src, wav, rec2, nt, sponge_width=5, sponge_alpha=0.05, variant=v, zchunk=zc,
+                          **extra)
             if variant_info(v)["family"] == 3:
                 assert oracle.rel_l2(got["u"], ref2["u"]) <= TOL_F32, (v, zc)
                 assert oracle.rel_l2(got["traces"], ref2["traces"]) <= TOL_F32, (v, zc)

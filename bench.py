@@ -59,12 +59,37 @@ def measured_traffic(storage: str, tiling: dict):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(W, vel):
-    """The oracle as it is (NumPy, FP64, one thread) on a bounded sample of the
-    same workload: enough time steps of the full 512^3 grid for ~10 s."""
-    import math
+def _oracle_steps(args):
+    """Seconds for `steps` oracle steps of an n^3 serving shot (a worker of
+    the all-core sample; imports inside, so it runs in a fresh process)."""
+    n, steps, seed = args
+    import time as _t
 
     import oracle
+    from synth import COURANT, ricker
+    from synth.velocity import layered_profile
+
+    vel = np.broadcast_to(layered_profile(n, seed)[:, None, None], (n, n, n)).astype(np.float32)
+    dt = COURANT * 10.0 / 4500.0
+    rec = np.array([[x, n // 2, 4] for x in range(n)])
+    t0 = _t.perf_counter()
+    oracle.forward(vel, 10.0, dt, (n // 2, n // 2, 4), ricker(steps, dt, 15.0), rec, nt=steps, sponge_width=20,
+                   sponge_alpha=0.015)
+    return _t.perf_counter() - t0
+
+
+def cpu_baseline(W, vel):
+    """The oracle as it is (NumPy, FP64, one thread per process), timed on
+    bounded samples: the headline value is enough time steps of the full
+    512^3 workload for ~10 s; beside it the whole 64^3 x 200 workload, and an
+    all-core estimate of serving shots/s (one process per core, each a few
+    steps of a 128^3 serving shot, extrapolated to the stream's mean of
+    1250 steps)."""
+    import math
+    from concurrent.futures import ProcessPoolExecutor
+
+    import oracle
+    from synth import workload
 
     def timed(steps):
         wav = W.wavelet(steps)
@@ -76,9 +101,28 @@ def cpu_baseline(W, vel):
     t1 = timed(1)
     steps = 1 if t1 >= 10.0 else min(8, math.ceil(10.0 / t1))
     t = timed(steps) if steps > 1 else t1
-    return {"value": round(W.npts * steps / t / 1e9, 5), "unit": "Gpts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} time steps of the {W.name} workload (sponge, source, 512x512 receivers), "
-                      f"FP64 NumPy oracle, single thread, {t:.1f} s; host reports {os.cpu_count()} CPUs"}
+    out = {"value": round(W.npts * steps / t / 1e9, 5), "unit": "Gpts/s", "cores": 1, "kind": "oracle",
+           "sample": f"{steps} time steps of the {W.name} workload (sponge, source, 512x512 receivers), "
+                     f"FP64 NumPy oracle, single thread, {t:.1f} s; host reports {os.cpu_count()} CPUs"}
+    S = workload("small")
+    t0 = time.perf_counter()
+    oracle.forward(S.velocity(), S.h, S.dt, S.src, S.wavelet(), S.rec, nt=S.nt)
+    ts = time.perf_counter() - t0
+    out["small_full_run"] = {"workload": f"{S.name} x {S.nt} steps (whole run)", "seconds": round(ts, 2),
+                             "gpts_per_s": round(S.npts * S.nt / ts / 1e9, 5), "cores": 1}
+    procs = max(1, min(16, os.cpu_count() or 1))
+    per = 4
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(procs) as pool:
+        secs = list(pool.map(_oracle_steps, [(128, per, 5000 + i) for i in range(procs)]))
+    wall = time.perf_counter() - t0
+    step_s = max(secs) / per
+    out["serving_all_cores"] = {
+        "sample": f"{procs} processes, each {per} steps of a 128^3 serving shot (sponge 20, line of receivers)",
+        "cores": procs, "s_per_step_per_process": round(step_s, 4),
+        "shots_per_s_128_extrapolated": round(procs / (step_s * 1250), 5),
+        "note": "extrapolated to 1250 steps per shot; 128^3 is the smallest serving grid", "wall_s": round(wall, 1)}
+    return out
 
 
 _PROBE = None
@@ -359,6 +403,47 @@ def kernel_study_leg(nt: int = 20) -> dict:
     return out
 
 
+def temporal_blocking_leg() -> dict:
+    """Two time steps per pass (time_block = 2) against one step per pass, on
+    the cache-resident 256^3 grid (the fields fit the 256 MB last-level
+    cache) and on the 512^3 grid: Gpts/s (points x time steps / time) and
+    each form's algorithmic bytes per point-step (one step per pass: 16 B;
+    a pass: A^n, A^{n-1}, m read and A^{n+1}, A^{n+2} written, 20 B for two
+    steps, 10 B per step)."""
+    import torch
+
+    from paper_2404_04441_amd import Solver
+    from synth import workload
+    from synth.velocity import smooth_random_torch
+    from synth.workloads import line_receivers
+
+    W = workload("precision")
+    dev = torch.device("cuda:0")
+    out = {"note": "smooth random model, Dirichlet, centre source, line of receivers; kernel time only"}
+    for n in (256, 512):
+        v = smooth_random_torch((n, n, n), seed=3, device=dev)
+        rec = line_receivers(n, n // 2, 4)
+        steps = 200 if n <= 256 else 60
+        wav = torch.from_numpy(W.wavelet(steps)).to(dev)
+        tr = torch.empty((steps, len(rec)), dtype=torch.float32, device=dev)
+        row = {}
+        for name, kw, bpp in (("one_step_tuned", {}, 16), ("one_step_cached_policy", dict(cache_hint=1), 16),
+                              ("two_steps_per_pass", dict(time_block=2), 10),
+                              ("two_steps_per_pass_zchunk64", dict(time_block=2, zchunk=64), 10)):
+            s = Solver(v, W.h, W.dt, src=(n // 2, n // 2, n // 2), rec=rec, **kw)
+            s.run(4, wav, tr)
+            r = kernel_rate(s, steps, wav, tr, n ** 3, bpp)
+            r["tiling"] = s.tiling()
+            s.close()
+            row[name] = r
+        out[f"{n}^3"] = row
+        print(f"[bench] temporal blocking {n}^3: " + ", ".join(f"{k} {r['gpts_per_s']}" for k, r in row.items()),
+              file=sys.stderr, flush=True)
+        del v
+        torch.cuda.empty_cache()
+    return out
+
+
 def gradient_leg() -> dict:
     """The 256^3 two-layer gradient workload (800 steps, sqrt(T) checkpoints):
     time of the velocity gradient against the time of the forward run."""
@@ -396,12 +481,17 @@ def gradient_leg() -> dict:
     t_grad = (_t.perf_counter() - t0) / 3
     misfit = 0.5 * float((resid.double() ** 2).sum())
     s.close()
-    bytes_per_pt_step = 60  # forward with checkpoints 16 + recompute 16 + adjoint step 28
+    # per gradient point-step: forward with checkpoints 16 + recomputation 16 +
+    # storing it 4 + adjoint step 16 + reading the forward field 4 + the
+    # imaging accumulator read and written 8
+    bytes_per_pt_step = 64
     return {"workload": f"{W.name}, {W.nt} steps, two-layer model, smoothed start, 256x256 receivers, "
                         f"checkpoint every {int(np.ceil(np.sqrt(W.nt)))} steps",
             "forward_s": round(t_fwd, 4), "gradient_s": round(t_grad, 4), "ratio": round(t_grad / t_fwd, 3),
             "gradient_gpts_per_s": round(W.npts * W.nt / t_grad / 1e9, 2),
             "gradient_gb_per_s": round(bytes_per_pt_step * W.npts * W.nt / t_grad / 1e9, 1),
+            "bytes_per_gradient_point_step": bytes_per_pt_step,
+            "roofline_frac": round(bytes_per_pt_step * W.npts * W.nt / t_grad / 1e9 / PEAK_HBM_GBS, 4),
             "misfit": misfit, "grad_finite": bool(torch.isfinite(grad).all().item())}
 
 
@@ -502,6 +592,10 @@ def main():
                     help="run only the 1024^3 kernel study (3D gmem/smem vs 2.5D shapes) and print its JSON")
     ap.add_argument("--cpml-only", action="store_true",
                     help="run only the 512^3 CPML leg (fused and unfused shapes) and print its JSON")
+    ap.add_argument("--precision-only", action="store_true",
+                    help="run only the 1024^3 storage forms (float32, 16-bit, 16-bit with 16-bit m) and print JSON")
+    ap.add_argument("--gradient-only", action="store_true",
+                    help="run only the 256^3 x 800 gradient leg and print its JSON")
     ap.add_argument("--size-probe", type=int, default=0,
                     help="run only the N^3 size probe (HIP stream ceiling + tuned float32 step) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -527,6 +621,12 @@ def main():
         if args.copy_calibration:
             copy_calibration(torch.device("cuda:0"))
         print(json.dumps({"size_probe": size_probe(args.size_probe)}), flush=True)
+        return
+    if args.precision_only:
+        print(json.dumps({"precision_1024": precision_leg()}), flush=True)
+        return
+    if args.gradient_only:
+        print(json.dumps({"gradient_256": gradient_leg()}), flush=True)
         return
     if args.serving_only:
         out = {"small_shot_probe": small_shot_probe()}
@@ -619,6 +719,7 @@ def main():
         del v_dev
         out["precision_1024"] = precision_leg()
         out["kernel_study_1024"] = kernel_study_leg()
+        out["temporal_blocking"] = temporal_blocking_leg()
         out["gradient_256"] = gradient_leg()
         print(f"[bench] gradient: {out['gradient_256']}", file=sys.stderr, flush=True)
     if args.serving > 0:

@@ -138,6 +138,16 @@ typedef struct {
  * alpha 0.015, unit spacings and dt (callers set the grid and dt), tune = 1. */
 void wave_params_init(wave_params *p);
 
+/* The largest stable time step for velocities up to vmax on p's grid
+ * spacing (the test wave_create applies, WAVE_EUNSTABLE above it, once it has
+ * read the velocity's maximum): the leapfrog of the update in paper Sec. II
+ * is stable iff (vmax dt)^2 lambda_max <= 4, with lambda_max = 2048/315 *
+ * sum_a h_a^-2 the largest eigenvalue magnitude of the Laplacian (Eq. 1's
+ * stencil at the Nyquist wavenumber on each axis), so
+ * dt_max = 2 / (vmax sqrt(2048/315 sum_a h_a^-2)).  Host only.  Errors:
+ * WAVE_EINVAL (null pointer, vmax or a spacing not finite and positive). */
+int wave_stable_dt(const wave_params *p, double vmax, double *dt_max);
+
 /* Bytes of device workspace wave_create needs for `p`: m = (v dt)^2, the
  * wavefields of the update (two float32 fields, or three 16-bit fields A,
  * A', V), the sponge tables, the receiver map and, with adjoint != 0, the

@@ -19,7 +19,7 @@ STORAGE = {"f32": WAVE_F32, "f16": WAVE_F16, "bf16": WAVE_BF16}
 
 # Every symbol include/wave.h declares.
 EXPORTS = (
-    "wave_params_init", "wave_workspace_bytes", "wave_create", "wave_create_static",
+    "wave_params_init", "wave_stable_dt", "wave_workspace_bytes", "wave_create", "wave_create_static",
     "wave_reset", "wave_step", "wave_run",
     "wave_adjoint", "wave_read_field", "wave_write_field", "wave_time_index", "wave_state_bytes", "wave_save_state", "wave_load_state",
     "wave_sync_status", "wave_destroy", "wave_tiling",
@@ -76,6 +76,7 @@ def lib():
         L.wave_params_init.argtypes = [P(WaveParams)]
         L.wave_params_init.restype = None
         L.wave_workspace_bytes.argtypes = [P(WaveParams), P(sz)]
+        L.wave_stable_dt.argtypes = [P(WaveParams), ctypes.c_double, P(ctypes.c_double)]
         L.wave_create.argtypes = [P(WaveParams), vp, vp, sz, vp, P(vp)]
         L.wave_create_static.argtypes = [P(WaveParams), vp, vp, P(vp)]
         L.wave_reset.argtypes = [vp]

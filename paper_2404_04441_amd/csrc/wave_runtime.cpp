@@ -692,6 +692,18 @@ void wave_params_init(wave_params *p) {
   p->tune = 1;
 }
 
+int wave_stable_dt(const wave_params *p, double vmax, double *dt_max) {
+  if (!p || !dt_max || !(vmax > 0.0) || !std::isfinite(vmax)) return WAVE_EINVAL;
+  if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dz)) return WAVE_EINVAL;
+  // leapfrog u+ = 2u - u- + (v dt)^2 L u is stable iff (v dt)^2 lambda <= 4 for
+  // every eigenvalue magnitude lambda of -L; the largest is the stencil's
+  // symbol at the Nyquist wavenumber, 2048/315 per axis, times sum_a h_a^-2
+  const double peak = 2048.0 / 315.0;
+  const double s = peak * (1.0 / (p->dx * p->dx) + 1.0 / (p->dy * p->dy) + 1.0 / (p->dz * p->dz));
+  *dt_max = 2.0 / (vmax * std::sqrt(s));
+  return WAVE_OK;
+}
+
 int wave_workspace_bytes(const wave_params *p, size_t *bytes) {
   if (!bytes) return WAVE_EINVAL;
   Layout L;
@@ -829,9 +841,9 @@ int create_ctx(const wave_params *p, const float *vel_dev, void *ws_dev, size_t 
   if (!rc) {
     float vmax;
     std::memcpy(&vmax, &back.vmax_bits, 4);
-    const double peak = 2048.0 / 315.0;  // max |symbol| of the 1D stencil, at the Nyquist wavenumber
     const double Mmax = static_cast<double>(vmax) * p->dt * static_cast<double>(vmax) * p->dt;
-    if (Mmax * peak * (ix2 + iy2 + iz2) > 4.0 * (1.0 + 1e-12)) rc = WAVE_EUNSTABLE;
+    double dt_max = 0.0;
+    if (wave_stable_dt(p, vmax, &dt_max) != WAVE_OK || p->dt > dt_max * (1.0 + 1e-12)) rc = WAVE_EUNSTABLE;
     // 16-bit scale bound: |M L A| <= Mmax (|k0| + sum_{a,m} 2 |c_m| / h_a^2) max|A|
     double kabs = 0.0;
     for (int m = 1; m <= 4; ++m) kabs += 2.0 * std::fabs(kC[m]) * (ix2 + iy2 + iz2);

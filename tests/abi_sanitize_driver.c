@@ -106,6 +106,14 @@ int main(void) {
   CHECK(wave_run(NULL, 1, NULL, NULL) == WAVE_EINVAL && wave_adjoint(NULL, 1, NULL, NULL, NULL) == WAVE_EINVAL);
   CHECK(wave_read_field(NULL, 0, NULL) == WAVE_EINVAL && wave_workspace_bytes(NULL, &b) == WAVE_EINVAL);
   CHECK(wave_write_field(NULL, 0, NULL) == WAVE_EINVAL);
+  {
+    wave_params q;
+    double dtmax = 0.0;
+    wave_params_init(&q);
+    q.dx = q.dy = q.dz = 10.0;
+    CHECK(wave_stable_dt(&q, 4500.0, &dtmax) == WAVE_OK && dtmax > 0.0);
+    CHECK(wave_stable_dt(&q, -1.0, &dtmax) == WAVE_EINVAL && wave_stable_dt(NULL, 1.0, &dtmax) == WAVE_EINVAL);
+  }
   int32_t tiling[3];
   CHECK(wave_tiling(NULL, tiling) == WAVE_EINVAL);
   wave_params_init(NULL);

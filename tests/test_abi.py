@@ -256,3 +256,28 @@ def test_model_bits_validation(lib):
     p.model_bits = 16
     assert lib.wave_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == L.WAVE_OK
     assert b.value < full  # m as 2-byte codes
+
+
+def test_stability_limit_on_the_host(lib):
+    """The time-step limit wave_create enforces, as a host function: against
+    the oracle's leapfrog stability bound (dense-operator pinned) on a cubic
+    grid, the anisotropic formula, and the reading of "CFL 0.5" the workloads
+    use (half the limit)."""
+    import oracle
+    from synth import COURANT
+
+    p = L.WaveParams()
+    lib.wave_params_init(ctypes.byref(p))
+    p.dx = p.dy = p.dz = 10.0
+    dt = ctypes.c_double()
+    assert lib.wave_stable_dt(ctypes.byref(p), 4500.0, ctypes.byref(dt)) == L.WAVE_OK
+    assert abs(dt.value * 4500.0 / 10.0 - oracle.stability_courant(3)) < 1e-12
+    assert abs(COURANT / (dt.value * 4500.0 / 10.0) - 0.5) < 1e-12
+    p.dx, p.dy, p.dz = 10.0, 12.0, 9.0
+    assert lib.wave_stable_dt(ctypes.byref(p), 3000.0, ctypes.byref(dt)) == L.WAVE_OK
+    peak = float(oracle.symbol_peak(4))
+    want = 2.0 / (3000.0 * (peak * (1 / 100 + 1 / 144 + 1 / 81)) ** 0.5)
+    assert abs(dt.value / want - 1) < 1e-12
+    assert lib.wave_stable_dt(ctypes.byref(p), 0.0, ctypes.byref(dt)) == L.WAVE_EINVAL
+    assert lib.wave_stable_dt(ctypes.byref(p), float("nan"), ctypes.byref(dt)) == L.WAVE_EINVAL
+    assert lib.wave_stable_dt(None, 3000.0, ctypes.byref(dt)) == L.WAVE_EINVAL

@@ -444,9 +444,10 @@ def temporal_blocking_leg() -> dict:
     return out
 
 
-def gradient_leg() -> dict:
+def gradient_leg(nt: int = 0, reps: int = 3) -> dict:
     """The 256^3 two-layer gradient workload (800 steps, sqrt(T) checkpoints):
-    time of the velocity gradient against the time of the forward run."""
+    time of the velocity gradient against the time of the forward run
+    (nt > 0: that many steps instead, for short profiled runs)."""
     import time as _t
 
     import numpy as np
@@ -457,41 +458,42 @@ def gradient_leg() -> dict:
     from synth.velocity import smooth_along_z
 
     W = workload("gradient")
+    nt = nt or W.nt
     dev = torch.device("cuda:0")
     v_true = W.velocity()
     v0 = smooth_along_z(v_true, 8.0)
-    wav = torch.from_numpy(W.wavelet()).to(dev)
+    wav = torch.from_numpy(W.wavelet(nt)).to(dev)
     st = Solver(torch.from_numpy(v_true).to(dev), W.h, W.dt, src=W.src, rec=W.rec)
-    d_obs = st.run(W.nt, wav).clone()
+    d_obs = st.run(nt, wav).clone()
     st.close()
-    s = Solver(torch.from_numpy(v0).to(dev), W.h, W.dt, src=W.src, rec=W.rec, adjoint=True, nt_max=W.nt)
-    tr = s.run(W.nt, wav)
+    s = Solver(torch.from_numpy(v0).to(dev), W.h, W.dt, src=W.src, rec=W.rec, adjoint=True, nt_max=nt)
+    tr = s.run(nt, wav)
     resid = (tr - d_obs).contiguous()
-    grad = s.adjoint(W.nt, wav, resid)  # warm-up
+    grad = s.adjoint(nt, wav, resid)  # warm-up
     torch.cuda.synchronize()
     t0 = _t.perf_counter()
-    for _ in range(3):
-        s.run(W.nt, wav, tr)
+    for _ in range(reps):
+        s.run(nt, wav, tr)
     torch.cuda.synchronize()
-    t_fwd = (_t.perf_counter() - t0) / 3
+    t_fwd = (_t.perf_counter() - t0) / reps
     t0 = _t.perf_counter()
-    for _ in range(3):
-        s.adjoint(W.nt, wav, resid, grad)
+    for _ in range(reps):
+        s.adjoint(nt, wav, resid, grad)
     torch.cuda.synchronize()
-    t_grad = (_t.perf_counter() - t0) / 3
+    t_grad = (_t.perf_counter() - t0) / reps
     misfit = 0.5 * float((resid.double() ** 2).sum())
     s.close()
     # per gradient point-step: forward with checkpoints 16 + recomputation 16 +
     # storing it 4 + adjoint step 16 + reading the forward field 4 + the
     # imaging accumulator read and written 8
     bytes_per_pt_step = 64
-    return {"workload": f"{W.name}, {W.nt} steps, two-layer model, smoothed start, 256x256 receivers, "
-                        f"checkpoint every {int(np.ceil(np.sqrt(W.nt)))} steps",
+    return {"workload": f"{W.name}, {nt} steps, two-layer model, smoothed start, 256x256 receivers, "
+                        f"checkpoint every {int(np.ceil(np.sqrt(nt)))} steps",
             "forward_s": round(t_fwd, 4), "gradient_s": round(t_grad, 4), "ratio": round(t_grad / t_fwd, 3),
-            "gradient_gpts_per_s": round(W.npts * W.nt / t_grad / 1e9, 2),
-            "gradient_gb_per_s": round(bytes_per_pt_step * W.npts * W.nt / t_grad / 1e9, 1),
+            "gradient_gpts_per_s": round(W.npts * nt / t_grad / 1e9, 2),
+            "gradient_gb_per_s": round(bytes_per_pt_step * W.npts * nt / t_grad / 1e9, 1),
             "bytes_per_gradient_point_step": bytes_per_pt_step,
-            "roofline_frac": round(bytes_per_pt_step * W.npts * W.nt / t_grad / 1e9 / PEAK_HBM_GBS, 4),
+            "roofline_frac": round(bytes_per_pt_step * W.npts * nt / t_grad / 1e9 / PEAK_HBM_GBS, 4),
             "misfit": misfit, "grad_finite": bool(torch.isfinite(grad).all().item())}
 
 
@@ -623,10 +625,14 @@ def main():
         print(json.dumps({"size_probe": size_probe(args.size_probe)}), flush=True)
         return
     if args.precision_only:
-        print(json.dumps({"precision_1024": precision_leg()}), flush=True)
+        if args.copy_calibration:
+            copy_calibration(torch.device("cuda:0"))
+        print(json.dumps({"precision_1024": precision_leg(args.nt or 500)}), flush=True)
         return
     if args.gradient_only:
-        print(json.dumps({"gradient_256": gradient_leg()}), flush=True)
+        if args.copy_calibration:
+            copy_calibration(torch.device("cuda:0"))
+        print(json.dumps({"gradient_256": gradient_leg(args.nt, args.steps if args.nt else 3)}), flush=True)
         return
     if args.serving_only:
         out = {"small_shot_probe": small_shot_probe()}

@@ -41,6 +41,8 @@ struct Coef {
   float kx[4];     // c_m / dx^2, m = 1..4
   float ky[4];
   float kz[4];
+  float k0a[3];    // c0 / h_a^2 per axis: the fused CPML step sums each axis' second derivative
+                   // from its centre term (see step_kernel)
 };
 
 // Receivers forming a regular box, listed x fastest then y then z:

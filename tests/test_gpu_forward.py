@@ -55,7 +55,7 @@ def test_small_workload_parity():
     e_up = oracle.rel_l2(got["u_prev"], ref["u_prev"])
     _say(f"rel-L2 u={e_u:.3e} u_prev={e_up:.3e} traces={e_tr:.3e}")
     assert e_u <= TOL_F32 and e_up <= TOL_F32
-    assert e_tr <= 10 * TOL_F32
+    assert e_tr <= TOL_F32
 
 
 @functools.lru_cache(maxsize=None)

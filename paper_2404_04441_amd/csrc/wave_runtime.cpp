@@ -521,7 +521,7 @@ int do_reset(wave_ctx *w) {
 struct TuneEntry {
   int nx, ny, nz, storage, cache_hint, model_bits;
   bool cpml, adjoint;
-  Tiling t;
+  Tiling t, adj;  // forward step; adjoint step (adjoint contexts)
 };
 std::mutex g_tune_mu;
 std::vector<TuneEntry> g_tune_cache;
@@ -534,6 +534,7 @@ int tune_forward(wave_ctx *w) {
       if (e.nx == p.nx && e.ny == p.ny && e.nz == p.nz && e.storage == p.storage && e.cpml == w->cpml &&
           e.cache_hint == p.cache_hint && e.adjoint == (p.adjoint != 0) && e.model_bits == (p.model_bits == 16)) {
         w->fwd = e.t;
+        if (p.adjoint) w->adj = e.adj;
         w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
         return WAVE_OK;
       }
@@ -621,12 +622,80 @@ int tune_forward(wave_ctx *w) {
   w->p.src[0] = src_x;
   w->fwd = best;
   w->cpml_fused = w->cpml && variant_fuses_cpml(w->fwd.variant);
+  // Adjoint contexts: the adjoint step (two z queues, the forward field and
+  // the imaging accumulator on top of the forward step's streams) is timed on
+  // its own, on the zero fields with no residual (wave_adjoint clears every
+  // buffer it reads before use): every 2.5D shape at its automatic z-chunk,
+  // then the z-chunk list for the two fastest, the default kept unless
+  // another is more than 3% faster.  All compute the same bits.
+  if (!rc && p.adjoint) {
+    const Layout &L = w->L;
+    float *mu1 = reinterpret_cast<float *>(w->ws + L.mua);
+    float *mu2 = reinterpret_cast<float *>(w->ws + L.mub);
+    float *img = reinterpret_cast<float *>(w->ws + L.img);
+    float *seg = reinterpret_cast<float *>(w->ws + L.seg);
+    auto time_adj = [&](const Tiling &t) {
+      StepArgs b = base_args(w, t);
+      b.sx = -1;
+      b.img = img;
+      b.cur = mu1;
+      b.prev = mu2;
+      b.out = mu2;
+      b.fwd = seg;
+      if (w->fused_rec) b.box = w->box;
+      int r = 0;
+      for (int i = 0; i < 4 && !r; ++i) {
+        if (i == 1) r = hip_rc(hipEventRecord(e0, w->stream));
+        if (!r) r = hip_rc(launch_step(WAVE_F32, t.variant, true, b, w->stream));
+      }
+      if (!r) r = hip_rc(hipEventRecord(e1, w->stream));
+      if (!r) r = hip_rc(hipEventSynchronize(e1));
+      float ms = 0.f;
+      if (!r) r = hip_rc(hipEventElapsedTime(&ms, e0, e1));
+      if (r) rc = r;
+      return r ? -1.f : ms;
+    };
+    const Tiling dflt = w->adj;
+    std::vector<std::pair<float, Tiling>> ta{{time_adj(dflt), dflt}};
+    for (int v = 0; v < variant_count() && !rc; ++v) {
+      const Variant info = variant_info(v);
+      if (info.family != 0 || p.nx % info.vec || v == dflt.variant) continue;
+      wave_params q = p;
+      q.variant = v;
+      q.zchunk = 0;
+      const Tiling t = make_tiling(&q, v);
+      ta.emplace_back(time_adj(t), t);
+    }
+    std::vector<std::pair<float, Tiling>> top(ta.begin(), ta.end());
+    std::sort(top.begin(), top.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    if (top.size() > 2) top.resize(2);
+    for (const auto &c : top) {
+      wave_params q = p;
+      q.variant = c.second.variant;
+      for (int zc : {9, 18, 27, 36, 45, 72, 99}) {
+        if (rc || zc >= p.nz) break;
+        q.zchunk = zc;
+        const Tiling t = make_tiling(&q, q.variant);
+        if (t.zchunk != c.second.zchunk) ta.emplace_back(time_adj(t), t);
+      }
+    }
+    if (!rc) {
+      const float base_ms = ta.front().first;
+      float best_ms = base_ms;
+      for (const auto &c : ta)
+        if (c.first > 0.f && c.first < best_ms) {
+          best_ms = c.first;
+          w->adj = c.second;
+        }
+      if (best_ms > 0.97f * base_ms) w->adj = dflt;
+    }
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (!rc) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune_cache.push_back(
-        TuneEntry{p.nx, p.ny, p.nz, p.storage, p.cache_hint, p.model_bits == 16, w->cpml, p.adjoint != 0, best});
+    g_tune_cache.push_back(TuneEntry{p.nx, p.ny, p.nz, p.storage, p.cache_hint, p.model_bits == 16, w->cpml,
+                                     p.adjoint != 0, best, w->adj});
   }
   return rc;
 }

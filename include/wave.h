@@ -94,10 +94,13 @@ typedef struct {
                                 (without CPML or adjoint), and for float32 forward runs without
                                 CPML or adjoint also the 3D-blocked gmem and smem shapes.  It
                                 keeps the fastest (the fixed rule's choice unless another is more
-                                than 3% faster); the choice is cached per (nx, ny, nz, storage,
-                                CPML, adjoint, cache_hint) for the life of the process.  Every
-                                choice computes the same bits; wave_tiling reports it.  0: the
-                                fixed automatic rule (measured: 30-50% slower at some sizes) */
+                                than 3% faster).  With adjoint != 0 it also times the adjoint
+                                step's shapes and z-chunks on their own and keeps the fastest the
+                                same way.  The choices are cached per (nx, ny, nz, storage, CPML,
+                                adjoint, cache_hint, model_bits) for the life of the process.
+                                Every choice computes the same bits; wave_tiling reports the
+                                forward one.  0: the fixed automatic rule (measured: 30-50%
+                                slower at some sizes) */
   int32_t cpml_width;        /* >0: CPML absorbing layers of this many nodes on all six faces (the
                                 boundary of paper Sec. II / IV-A; float32, forward only, needs
                                 sponge_width = 0, 2*cpml_width <= nx, ny, nz, nx*ny*nz < 2^31 and
@@ -246,8 +249,9 @@ int wave_time_index(wave_t w, int32_t *n);
  * variant (1 .. wave_variant_count()-1; see wave_variant_info), the z-chunk
  * in planes, and the cache policy (0 nontemporal, 1 regular; see
  * cache_hint).  Passing these back as variant, zchunk and cache_hint (with
- * tune = 0) reproduces the configuration.  Errors: WAVE_EINVAL for a null
- * argument. */
+ * tune = 0) reproduces the forward configuration (an adjoint context then
+ * runs its adjoint step in the same shape, with the same bits).  Errors:
+ * WAVE_EINVAL for a null argument. */
 int wave_tiling(wave_t w, int32_t *out);
 
 /* Shot snapshots: the complete state of a forward run after its last

@@ -37,6 +37,8 @@ static_assert(sizeof(StepState) == 128, "state block layout");
 // with c0 = -2 sum_m c_m this is the same operator, but no large centre term
 // is summed against its neighbours (in float32 that cancellation dominated
 // the rounding error of a long run; see the tolerance notes in the tests).
+// The one exception is the step with the CPML x terms fused in, which sums
+// each axis from its centre weight k0a (see step_kernel).
 struct Coef {
   float kx[4];     // c_m / dx^2, m = 1..4
   float ky[4];

@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(256) cpml_fix_yz_kernel(CpmlArgs c, const floa
 #pragma unroll
     for (int e = 0; e < VEC; ++e) d2[e] = 0.f;
 #pragma unroll
-    for (int k = 1; k <= R; ++k) {  // second differences from the centre, as in the step kernel
+    for (int k = 1; k <= R; ++k) {  // second differences from the centre (no large centre term)
       float up[VEC], dn[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) up[e] = dn[e] = 0.f;

@@ -271,6 +271,7 @@ def storage_forms_leg(W, vel_dev, nt: int) -> dict:
                    sponge_alpha=W.sponge_alpha, **_storage_kw(fmt))
         s.run(20, wav, traces)
         out[fmt] = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT[fmt], SURVEY_16BIT_BYTES)
+        out[fmt]["tiling"] = s.tiling()
         s.close()
     return out
 
@@ -329,6 +330,7 @@ def precision_leg(nt: int = 500) -> dict:
         s.run(10, wav, traces)
         out[fmt] = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT[fmt],
                                None if fmt == "f32" else SURVEY_16BIT_BYTES)
+        out[fmt]["tiling"] = s.tiling()
         s.close()
         print(f"[bench] precision 1024^3 {fmt}: {out[fmt]}", file=sys.stderr, flush=True)
     del vel

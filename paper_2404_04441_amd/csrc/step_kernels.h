@@ -123,6 +123,7 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
 constexpr int kNT = 2;                  // nontemporal cache policy bit
 
@@ -639,7 +640,12 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   for (int s = 0; s < PD; ++s) load_stage(stg[s], zb + s);
 
   const float wsrc = (!ADJ && a.sx >= 0) ? a.wavelet[n] * a.src_scale : 0.f;
+  // 16-bit storage: running maxima of the stored magnitudes kept as 16-bit
+  // patterns with the sign cleared, both halves of a word per instruction;
+  // for f16 and bf16 the magnitude order of finite values is the unsigned
+  // order of those bits, so the maxima decode to max |stored| exactly
   float amax_loc = 0.f, amaxv_loc = 0.f;
+  u16x2 amax_bits = {0, 0}, amaxv_bits = {0, 0};
 
   // Laplacian of Eq. 1 at the VEC nodes of row j of this lane: centre and z
   // neighbours from the queue Q, x neighbours from a window of the LDS row,
@@ -803,7 +809,8 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       float wsp[VEC];
 #pragma unroll
       for (int i = 0; i < VEC; ++i) wsp[i] = (!ADJ && z == a.sz && i == srci) ? wsrc : 0.f;
-      float outv[RY][VEC];
+      float outv[S == kF32 ? RY : 1][S == kF32 ? VEC : 1];  // float32: A^{n+1} of the plane's rows
+      Words<NA> rkeep[S != kF32 ? RY : 1];                  // 16-bit: the stored rows (receivers)
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
         float lap[VEC], lax[3][VEC];
@@ -855,7 +862,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
             v[i] = fmaf(g, c, vv[i]);
           }
         }
-        if (S == kF32) {
+        if constexpr (S == kF32) {
           st_words<NA, NTP>(row_put<S, VEC>(v), rO, vrow[j], sz0);
 #pragma unroll
           for (int i = 0; i < VEC; ++i) outv[j][i] = v[i];
@@ -870,12 +877,11 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
           st_words<NA, NTP>(ra, rO, vrow[j], sz0);
           st_words<NA, NTP>(rv, rVo, vrow[j], sz0);
 #pragma unroll
-          for (int i = 0; i < VEC; ++i) {
-            const float stored = row_get<S>(ra, i);
-            outv[j][i] = stored * inv_next;
-            amax_loc = fmaxf(amax_loc, fabsf(stored));
-            amaxv_loc = fmaxf(amaxv_loc, fabsf(row_get<S>(rv, i)));
+          for (int k = 0; k < Words<NA>::N; ++k) {
+            amax_bits = __builtin_elementwise_max(amax_bits, __builtin_bit_cast(u16x2, ra.w[k] & 0x7fff7fffu));
+            amaxv_bits = __builtin_elementwise_max(amaxv_bits, __builtin_bit_cast(u16x2, rv.w[k] & 0x7fff7fffu));
           }
+          rkeep[S != kF32 ? j : 0] = ra;
         }
         if constexpr (ADJ) {
           float lapF[VEC], im[VEC], laxF[3][VEC];
@@ -891,14 +897,21 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
         for (int j = 0; j < RY; ++j)
 #pragma unroll
           for (int i = 0; i < VEC; ++i)
-            if (ryi[j] >= 0 && rxi[i] >= 0)
-              a.traces[static_cast<size_t>(n) * a.nrec + (rzi * a.box.cny + ryi[j]) * a.box.cnx + rxi[i]] =
-                  outv[j][i];
+            if (ryi[j] >= 0 && rxi[i] >= 0) {
+              float val;
+              if constexpr (S == kF32)
+                val = outv[j][i];
+              else
+                val = row_get<S>(rkeep[j], i) * inv_next;
+              a.traces[static_cast<size_t>(n) * a.nrec + (rzi * a.box.cny + ryi[j]) * a.box.cnx + rxi[i]] = val;
+            }
       }
     });
   }
 
   if (S != kF32) {  // one order-independent atomic per workgroup and field
+    amax_loc = row_get<S>(Words<2>{{static_cast<uint32_t>(amax_bits.x > amax_bits.y ? amax_bits.x : amax_bits.y)}}, 0);
+    amaxv_loc = row_get<S>(Words<2>{{static_cast<uint32_t>(amaxv_bits.x > amaxv_bits.y ? amaxv_bits.x : amaxv_bits.y)}}, 0);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       amax_loc = fmaxf(amax_loc, __shfl_xor(amax_loc, off, 64));

@@ -81,10 +81,11 @@ def _oracle_steps(args):
 def cpu_baseline(W, vel):
     """The oracle as it is (NumPy, FP64, one thread per process), timed on
     bounded samples: the headline value is enough time steps of the full
-    512^3 workload for ~10 s; beside it the whole 64^3 x 200 workload, and an
-    all-core estimate of serving shots/s (one process per core, each a few
-    steps of a 128^3 serving shot, extrapolated to the stream's mean of
-    1250 steps)."""
+    512^3 workload for ~10 s; beside it the whole 64^3 x 200 workload, the
+    whole 128^3 x 500 crop of the 1024^3 workload, 10 forward steps of the
+    256^3 gradient workload, and an all-core estimate of serving shots/s (one
+    process per core, each a few steps of a 128^3 serving shot, extrapolated
+    to the stream's mean of 1250 steps)."""
     import math
     from concurrent.futures import ProcessPoolExecutor
 
@@ -110,6 +111,20 @@ def cpu_baseline(W, vel):
     ts = time.perf_counter() - t0
     out["small_full_run"] = {"workload": f"{S.name} x {S.nt} steps (whole run)", "seconds": round(ts, 2),
                              "gpts_per_s": round(S.npts * S.nt / ts / 1e9, 5), "cores": 1}
+    C = workload("precision_crop")
+    t0 = time.perf_counter()
+    oracle.forward(C.velocity(), C.h, C.dt, C.src, C.wavelet(), C.rec, nt=C.nt)
+    tc = time.perf_counter() - t0
+    out["crop_full_run"] = {"workload": f"{C.name} x {C.nt} steps (whole run)", "seconds": round(tc, 2),
+                            "gpts_per_s": round(C.npts * C.nt / tc / 1e9, 5), "cores": 1}
+    G = workload("gradient")
+    gsteps = 10
+    t0 = time.perf_counter()
+    oracle.forward(G.velocity(), G.h, G.dt, G.src, G.wavelet(gsteps), G.rec, nt=gsteps)
+    tg = time.perf_counter() - t0
+    out["gradient_workload_forward"] = {
+        "workload": f"{G.name}: {gsteps} forward steps (the gradient also runs the adjoint)",
+        "s_per_step": round(tg / gsteps, 4), "gpts_per_s": round(G.npts * gsteps / tg / 1e9, 5), "cores": 1}
     procs = max(1, min(16, os.cpu_count() or 1))
     per = 4
     t0 = time.perf_counter()

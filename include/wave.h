@@ -233,11 +233,15 @@ int wave_adjoint(wave_t w, int32_t nt, const float *wavelet_dev, const float *re
  * only, WAVE_EINVAL otherwise): the stored V^n = A^n - g A^{n-1}. */
 int wave_read_field(wave_t w, int32_t which, float *out_dev);
 
-/* Set a stored time level from in_dev (device float32 [nz][ny][nx]),
- * float32 storage only (WAVE_EINVAL otherwise): which = 0 writes A^n, which =
- * 1 the stored (undamped) A^{n-1}, so that the next wave_step advances from a
- * given initial state (paper Sec. II's update applied to any wavefield; the
- * inverse of wave_read_field).  The step counter is unchanged.  Enqueued on
+/* Set a stored time level from in_dev (device float32 [nz][ny][nx]), so
+ * that the next wave_step advances from a given state (paper Sec. II's update
+ * applied to any wavefield; the inverse of wave_read_field).  Float32
+ * storage: which = 0 writes A^n, which = 1 the stored (undamped) A^{n-1}.
+ * 16-bit storage: which = 0 writes A^n, which = 2 the stored V^n = A^n -
+ * g A^{n-1}, each rounded to nearest even at the power-of-two scale the step
+ * rule gives for the field's maximum (stored magnitudes below 2^14), with the
+ * field's scale and maximum records set as a step would leave them.  Other
+ * values of which: WAVE_EINVAL.  The step counter is unchanged.  Enqueued on
  * the context's stream; in_dev must stay valid until the stream reaches it. */
 int wave_write_field(wave_t w, int32_t which, const float *in_dev);
 

@@ -142,6 +142,11 @@ hipError_t launch_init_m(const float *vel, float *m, size_t n, float dt, StepSta
 hipError_t launch_encode_m16(const float *vel, uint16_t *codes, size_t n, float dt, float m_lo, float m_step,
                              hipStream_t s);
 hipError_t launch_bump(StepState *st, int count, hipStream_t s);
+// 16-bit storage: encode float32 x into a stored field of step n (dst; the
+// V field with v_field) at the exponent the bound rule gives for max |x|,
+// and set that field's exponent and stored-maximum records for step n
+hipError_t launch_encode_field(int storage, const float *x, void *dst, size_t n, StepState *st, bool v_field,
+                              hipStream_t s);
 hipError_t launch_decode(int storage, const void *field, float *out, size_t n, const StepState *st,
                          int slot_from_n_offset, bool v_field, hipStream_t s);
 hipError_t launch_decode_prev(int storage, const void *a, const void *v, float *out, const float *gx,

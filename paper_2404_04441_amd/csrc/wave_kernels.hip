@@ -371,6 +371,52 @@ __global__ void encode_m16_kernel(const float *__restrict__ vel, uint16_t *__res
   }
 }
 
+// Setting a 16-bit stored field from float32 values (wave_write_field): the
+// field's maximum record of step n first holds max |x| (float bits; the
+// values are non-negative, so unsigned order is float order), the encode
+// uses the exponent the step kernel's rule gives for that bound, and the
+// record then takes the largest stored magnitude, with the exponent beside it.
+__global__ void scale_record_clear_kernel(StepState *st, int v_field) {
+  if (threadIdx.x == 0) (v_field ? st->amax_v : st->amax)[st->n & 3] = 0u;
+}
+
+__global__ void __launch_bounds__(256) absmax_kernel(const float *__restrict__ x, size_t n, StepState *st,
+                                                     int v_field) {
+  __shared__ float part[4];
+  float mx = 0.f;
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    mx = fmaxf(mx, fabsf(x[i]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(&(v_field ? st->amax_v : st->amax)[st->n & 3],
+              __float_as_uint(fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]))));
+}
+
+template <int S>
+__global__ void encode_field_kernel(const float *__restrict__ x, typename Codec<S>::raw *__restrict__ dst, size_t n,
+                                    const StepState *st, int v_field) {
+  const float bound = __uint_as_float((v_field ? st->amax_v : st->amax)[st->n & 3]);
+  const float sc = exp2i(scale_exponent(bound));
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    dst[i] = Codec<S>::enc(x[i] * sc);
+}
+
+template <int S>
+__global__ void scale_record_kernel(StepState *st, int v_field) {
+  if (threadIdx.x != 0) return;
+  const int slot = st->n & 3;
+  uint32_t *rec = v_field ? st->amax_v : st->amax;
+  const float bound = __uint_as_float(rec[slot]);
+  const int e = scale_exponent(bound);
+  rec[slot] = __float_as_uint(fabsf(Codec<S>::dec(Codec<S>::enc(bound * exp2i(e)))));
+  (v_field ? st->exps_v : st->exps)[slot] = e;
+}
+
 __global__ void bump_kernel(StepState *st, int count) {
   if (threadIdx.x == 0) st->n += count;
 }
@@ -527,6 +573,23 @@ hipError_t launch_init_m(const float *vel, float *m, size_t n, float dt, StepSta
 hipError_t launch_encode_m16(const float *vel, uint16_t *codes, size_t n, float dt, float m_lo, float m_step,
                              hipStream_t s) {
   hipLaunchKernelGGL(encode_m16_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, vel, codes, n, dt, m_lo, m_step);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_field(int storage, const float *x, void *dst, size_t n, StepState *st, bool v_field,
+                              hipStream_t s) {
+  if (storage != kF16 && storage != kBF16) return hipErrorInvalidValue;
+  const int vf = v_field ? 1 : 0;
+  const dim3 g(grid_for(n, 256)), b(256);
+  hipLaunchKernelGGL(scale_record_clear_kernel, dim3(1), dim3(64), 0, s, st, vf);
+  hipLaunchKernelGGL(absmax_kernel, g, b, 0, s, x, n, st, vf);
+  if (storage == kF16) {
+    hipLaunchKernelGGL(encode_field_kernel<kF16>, g, b, 0, s, x, static_cast<uint16_t *>(dst), n, st, vf);
+    hipLaunchKernelGGL(scale_record_kernel<kF16>, dim3(1), dim3(64), 0, s, st, vf);
+  } else {
+    hipLaunchKernelGGL(encode_field_kernel<kBF16>, g, b, 0, s, x, static_cast<uint16_t *>(dst), n, st, vf);
+    hipLaunchKernelGGL(scale_record_kernel<kBF16>, dim3(1), dim3(64), 0, s, st, vf);
+  }
   return hipGetLastError();
 }
 

@@ -1098,9 +1098,15 @@ int wave_read_field(wave_t w, int32_t which, float *out_dev) {
 }
 
 int wave_write_field(wave_t w, int32_t which, const float *in_dev) {
-  if (!w || !in_dev || which < 0 || which > 1 || w->p.storage != WAVE_F32) return WAVE_EINVAL;
-  void *dst = w->field(which == 0 ? w->n : w->n + 3);
-  return hip_rc(hipMemcpyAsync(dst, in_dev, 4 * w->N, hipMemcpyDeviceToDevice, w->stream));
+  if (!w || !in_dev) return WAVE_EINVAL;
+  if (w->p.storage == WAVE_F32) {
+    if (which < 0 || which > 1) return WAVE_EINVAL;
+    void *dst = w->field(which == 0 ? w->n : w->n + 3);
+    return hip_rc(hipMemcpyAsync(dst, in_dev, 4 * w->N, hipMemcpyDeviceToDevice, w->stream));
+  }
+  if (which != 0 && which != 2) return WAVE_EINVAL;  // 16-bit storage keeps A^n and V^n
+  return hip_rc(launch_encode_field(w->p.storage, in_dev, which == 0 ? w->field(w->n) : w->fv, w->N, w->st,
+                                    which == 2, w->stream));
 }
 
 // Snapshot layout: 256-B header | step state | A fields 0 and 1 | V (16-bit)

@@ -171,8 +171,10 @@ class Solver:
         return out
 
     def write_field(self, which: int, field: torch.Tensor):
-        """Set A^n (which = 0) or the stored A^{n-1} (which = 1) from a float32
-        [nz, ny, nx] device tensor (float32 storage only)."""
+        """Set a stored time level from a float32 [nz, ny, nx] device tensor:
+        A^n (which = 0) and, with float32 storage, the stored A^{n-1} (which = 1)
+        or, with 16-bit storage, V^n (which = 2), encoded at the step rule's
+        scale for its maximum."""
         _dev_f32(field, "field")
         if tuple(field.shape) != self.shape:
             raise ValueError(f"field must have shape {self.shape}")

@@ -209,6 +209,156 @@ def test_one_step_encoding(fmt):
         assert np.abs(got[~live]).max(initial=0.0) <= 2.0 ** -99
 
 
+class _Gathered:
+    """A few nodes of a device array, gathered to the host and indexed
+    [z, y, x] like the array itself (nodes outside the grid read 0)."""
+
+    def __init__(self, shape, table):
+        self.shape = shape
+        self._t = table
+
+    def __getitem__(self, idx):
+        return self._t.get(tuple(int(i) for i in idx), 0.0)
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_write_field_encodes_at_the_rule_exponent(fmt):
+    """wave_write_field with 16-bit storage: A^n and V^n read back as the
+    input rounded to nearest even at the exponent the bound rule gives for its
+    maximum (stored magnitudes below 2^14), bit for bit."""
+    from oracle.storage import quantize, scale_exponent
+    from paper_2404_04441_amd import Solver
+
+    shape, h, vel, dt, nt, wav, rec, src, _ = ragged()
+    rng = np.random.default_rng(23)
+    s = Solver(torch.from_numpy(vel).cuda(), h, dt, src=src, rec=rec, storage=fmt)
+    for which, scale in ((0, 3.7), (2, 0.011)):
+        x = (scale * rng.standard_normal(shape)).astype(np.float32)
+        s.write_field(which, torch.from_numpy(x).cuda())
+        got = s.read_field(which).cpu().numpy().astype(np.float64)
+        e = scale_exponent(float(np.abs(x).max()))
+        want = quantize(x.astype(np.float64) * 2.0 ** e, fmt) * 2.0 ** -e
+        _say(f"{fmt} which={which}: exponent {e}, max stored {np.abs(want).max() * 2.0 ** e:.1f}")
+        assert np.abs(want).max() * 2.0 ** e < 2 ** 14 + 1
+        assert np.array_equal(got, want)
+    s.close()
+
+
+@pytest.mark.parametrize("fmt,bits", [("f16", 32), ("bf16", 32), ("f16", 16), ("bf16", 16)])
+def test_full_size_1024_one_step_encoding(fmt, bits):
+    """The 1024^3 precision workload in the configuration the benchmark times
+    (create-time tuning; z-chunks capped by the 2 GiB resource span), 16-bit
+    storage: A^n and V^n set to seeded random fields (so every tile edge and
+    z-chunk boundary carries data), one GPU step, checked at sampled nodes
+    (random, both sides of every tile edge and chunk boundary, the faces and
+    the source) as test_one_step_encoding checks it on the small grid: the
+    oracle's pointwise FP64 step from the stored A^n and V^n, the exponents
+    from the bound rule on the fields' maxima, rounding to the format; with m
+    in 16 bits on the velocity the codes represent."""
+    from oracle.storage import growth_bound_gamma, quantize, scale_exponent
+    from paper_2404_04441_amd import Solver, variant_info
+    from synth.velocity import smooth_random_torch
+
+    W = workload("precision")
+    dev = torch.device("cuda")
+    _say(f"case: 1024^3 precision workload, {fmt} storage, m in {bits} bits, one step from a random state")
+    vel = smooth_random_torch(W.shape, seed=3, device=dev)
+    wav = torch.from_numpy(W.wavelet(1)).to(dev)
+    tr = torch.zeros((1, len(W.rec)), dtype=torch.float32, device=dev)
+    s = Solver(vel, W.h, W.dt, src=W.src, rec=W.rec, storage=fmt, model_bits=bits)
+    s.reset()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1024 + bits)
+    s.write_field(0, torch.randn(W.shape, generator=gen, device=dev))
+    s.write_field(2, 0.05 * torch.randn(W.shape, generator=gen, device=dev))
+    A = s.read_field(0)
+    V = s.read_field(2)
+    a_max, v_max = float(A.abs().max()), float(V.abs().max())
+    tiling = s.tiling()
+    info = variant_info(tiling["variant"])
+    _say(f"tiling {tiling} {info}")
+    nz, ny, nx = W.shape
+    lo, hi = 0, 1024
+    tx, ty, tz = 64 * info["vec"], info["by"] * info["ry"], tiling["zchunk"]
+    edge = np.array([0, 1, 3, 4, 5, 1019, 1020, 1022, 1023])
+
+    def around(step):
+        e = np.arange(step, 1024, step)
+        return np.concatenate([e - 1, e, edge])
+
+    rng = np.random.default_rng(17)
+    pts = [rng.integers(lo, hi, (1500, 3)),
+           np.stack([rng.choice(around(tx), 1500), rng.choice(around(ty), 1500), rng.choice(around(tz), 1500)], 1),
+           np.array([W.src])]
+    pts = np.concatenate(pts).astype(np.int64)
+    offs = [(0, 0, 0)] + [o for m in range(1, 5) for o in
+                          ((m, 0, 0), (-m, 0, 0), (0, m, 0), (0, -m, 0), (0, 0, m), (0, 0, -m))]
+    need = sorted({(z + dz, y + dy, x + dx) for x, y, z in pts for dx, dy, dz in offs
+                   if 0 <= x + dx < nx and 0 <= y + dy < ny and 0 <= z + dz < nz})
+    idx = torch.from_numpy(np.array(need, dtype=np.int64)).to(dev)
+    a_tab = dict(zip(need, A[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy().tolist()))
+    p = torch.from_numpy(pts).to(dev)
+    Vc = V[p[:, 2], p[:, 1], p[:, 0]].double().cpu().numpy()
+    Ac = A[p[:, 2], p[:, 1], p[:, 0]].double().cpu().numpy()
+    vc = vel[p[:, 2], p[:, 1], p[:, 0]].double().cpu().numpy()
+    v_lo, v_hi = float(vel.min()), float(vel.max())
+    del A, V
+    s.step(1, wav, tr)
+    got_a = s.read_field(0)[p[:, 2], p[:, 1], p[:, 0]].double().cpu().numpy()
+    got_v = s.read_field(2)[p[:, 2], p[:, 1], p[:, 0]].double().cpu().numpy()
+    s.close()
+    dt = W.dt
+    if bits == 16:  # the velocity whose m the codes represent, at the sampled nodes (float32 as the library)
+        f = np.float32
+        t = vc.astype(f) * f(dt)
+        m = t * t
+        tlo, thi = f(v_lo) * f(dt), f(v_hi) * f(dt)
+        mlo = tlo * tlo
+        mstep = (thi * thi - mlo) / f(65535)
+        u = np.clip(np.rint((m - mlo) / mstep), 0, 65535)
+        vc = np.sqrt((u * float(mstep) + float(mlo)).astype(f).astype(np.float64)) / dt
+    # oracle pointwise step (no sponge: g = 1, so A^{n-1} = A^n - V^n at the node)
+    an = _Gathered(W.shape, a_tab)
+    ap = _Gathered(W.shape, {tuple(int(i) for i in (z, y, x)): Ac[i_] - Vc[i_]
+                             for i_, (x, y, z) in enumerate(pts)})
+    vv = _Gathered(W.shape, {tuple(int(i) for i in (z, y, x)): vc[i_] for i_, (x, y, z) in enumerate(pts)})
+    a_new = oracle.step_at(pts, an, ap, vv, W.h, dt, src=W.src, s_n=float(wav[0]))
+    v_new = a_new - Ac
+    hx, hy, hz = (W.h,) * 3 if np.isscalar(W.h) else W.h
+    c = oracle.second_derivative_weights(4)
+    sten = np.zeros(len(pts))
+    for i_, (x, y, z) in enumerate(pts):
+        ctr = an[z, y, x]
+        for (dx, dy, dz), ha in (((1, 0, 0), hx), ((0, 1, 0), hy), ((0, 0, 1), hz)):
+            for m_ in range(1, 5):
+                sten[i_] += abs(c[m_]) / ha ** 2 * (abs(an[z + m_ * dz, y + m_ * dy, x + m_ * dx] - ctr)
+                                                    + abs(an[z - m_ * dz, y - m_ * dy, x - m_ * dx] - ctr))
+    q = np.zeros(len(pts))
+    q[-1] = dt * dt * float(wav[0]) / (hx * hy * hz)
+    M = (dt * vc) ** 2
+    terms_v = np.abs(Vc) + M * sten + np.abs(q)
+    terms_a = np.abs(Ac) + terms_v
+    gamma = growth_bound_gamma(v_hi, W.h, dt)
+    bv = v_max + gamma * a_max + abs(q[-1])
+    for name, got, exact, e, terms in (("A", got_a, a_new, scale_exponent(a_max + bv), terms_a),
+                                       ("V", got_v, v_new, scale_exponent(bv), terms_v)):
+        emu = quantize(exact * 2.0 ** e, fmt) * 2.0 ** -e
+        scaled = got * 2.0 ** e
+        assert np.array_equal(quantize(scaled, fmt), scaled)  # values on the format's grid at that exponent
+        live = np.abs(exact) > 2.0 ** -100
+        diff = (got != emu) & live
+        frac = diff.sum() / live.sum()
+        step = np.maximum(ULP[fmt] * np.abs(emu * 2.0 ** e), TINY[fmt])
+        slack = 16 * 2.0 ** -24 * terms * 2.0 ** e
+        dist = np.abs(got - emu) * 2.0 ** e
+        worst = (dist / (step + slack))[live].max()
+        _say(f"{fmt} m{bits} {name}: exponent {e}, {diff.sum()} of {live.sum()} live sampled values differ, "
+             f"worst {worst:.2f} of (ulp + float32 evaluation bound)")
+        assert live.sum() > 1000
+        assert frac <= 1e-2 and worst <= 1.0 + 1e-9
+        assert np.abs(got[~live]).max(initial=0.0) <= 2.0 ** -99
+
+
 @functools.lru_cache(maxsize=None)
 def crop_reference(dtype_name="float64"):
     """The oracle's loop on the 128^3 crop, 500 steps, in float64 (the

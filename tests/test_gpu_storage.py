@@ -244,14 +244,16 @@ def test_write_field_encodes_at_the_rule_exponent(fmt):
     s.close()
 
 
+@pytest.mark.parametrize("name", ["precision", "large"])
 @pytest.mark.parametrize("fmt,bits", [("f16", 32), ("bf16", 32), ("f16", 16), ("bf16", 16)])
-def test_full_size_1024_one_step_encoding(fmt, bits):
-    """The 1024^3 precision workload in the configuration the benchmark times
-    (create-time tuning; z-chunks capped by the 2 GiB resource span), 16-bit
-    storage: A^n and V^n set to seeded random fields (so every tile edge and
-    z-chunk boundary carries data), one GPU step, checked at sampled nodes
-    (random, both sides of every tile edge and chunk boundary, the faces and
-    the source) as test_one_step_encoding checks it on the small grid: the
+def test_full_size_one_step_encoding(name, fmt, bits):
+    """The 1024^3 precision workload and the 512^3 workload (sponge, receiver
+    plane) in the configurations the benchmark times them in with 16-bit
+    storage (create-time tuning; z-chunks capped by the 2 GiB resource span):
+    A^n and V^n set to seeded random fields (so every tile edge and z-chunk
+    boundary carries data), one GPU step, checked at sampled nodes (random,
+    both sides of every tile edge and chunk boundary, the faces and the
+    source) as test_one_step_encoding checks it on the small grid: the
     oracle's pointwise FP64 step from the stored A^n and V^n, the exponents
     from the bound rule on the fields' maxima, rounding to the format; with m
     in 16 bits on the velocity the codes represent."""
@@ -259,13 +261,17 @@ def test_full_size_1024_one_step_encoding(fmt, bits):
     from paper_2404_04441_amd import Solver, variant_info
     from synth.velocity import smooth_random_torch
 
-    W = workload("precision")
+    W = workload(name)
     dev = torch.device("cuda")
-    _say(f"case: 1024^3 precision workload, {fmt} storage, m in {bits} bits, one step from a random state")
-    vel = smooth_random_torch(W.shape, seed=3, device=dev)
+    _say(f"case: {W.name} workload, {fmt} storage, m in {bits} bits, one step from a random state")
+    if name == "precision":
+        vel = smooth_random_torch(W.shape, seed=3, device=dev)
+    else:
+        vel = torch.from_numpy(W.velocity()).to(dev)
     wav = torch.from_numpy(W.wavelet(1)).to(dev)
     tr = torch.zeros((1, len(W.rec)), dtype=torch.float32, device=dev)
-    s = Solver(vel, W.h, W.dt, src=W.src, rec=W.rec, storage=fmt, model_bits=bits)
+    s = Solver(vel, W.h, W.dt, src=W.src, rec=W.rec, sponge_width=W.sponge_width, sponge_alpha=W.sponge_alpha,
+               storage=fmt, model_bits=bits)
     s.reset()
     gen = torch.Generator(device=dev)
     gen.manual_seed(1024 + bits)
@@ -278,16 +284,15 @@ def test_full_size_1024_one_step_encoding(fmt, bits):
     info = variant_info(tiling["variant"])
     _say(f"tiling {tiling} {info}")
     nz, ny, nx = W.shape
-    lo, hi = 0, 1024
     tx, ty, tz = 64 * info["vec"], info["by"] * info["ry"], tiling["zchunk"]
-    edge = np.array([0, 1, 3, 4, 5, 1019, 1020, 1022, 1023])
+    edge = np.array([0, 1, 3, 4, 5, 19, 20, 21, nx - 22, nx - 21, nx - 20, nx - 5, nx - 4, nx - 2, nx - 1])
 
     def around(step):
-        e = np.arange(step, 1024, step)
+        e = np.arange(step, nx, step)
         return np.concatenate([e - 1, e, edge])
 
     rng = np.random.default_rng(17)
-    pts = [rng.integers(lo, hi, (1500, 3)),
+    pts = [rng.integers(0, nx, (1500, 3)),
            np.stack([rng.choice(around(tx), 1500), rng.choice(around(ty), 1500), rng.choice(around(tz), 1500)], 1),
            np.array([W.src])]
     pts = np.concatenate(pts).astype(np.int64)
@@ -317,13 +322,17 @@ def test_full_size_1024_one_step_encoding(fmt, bits):
         mstep = (thi * thi - mlo) / f(65535)
         u = np.clip(np.rint((m - mlo) / mstep), 0, 65535)
         vc = np.sqrt((u * float(mstep) + float(mlo)).astype(f).astype(np.float64)) / dt
-    # oracle pointwise step (no sponge: g = 1, so A^{n-1} = A^n - V^n at the node)
+    # oracle pointwise step: A^{n-1} = (A^n - V^n) / g at the node (the stored
+    # V is A^n - g A^{n-1}); V^{n+1} = A^{n+1} - g A^n
+    gx, gy, gz = (oracle.sponge_profile(n_, W.sponge_width, W.sponge_alpha) for n_ in (nx, ny, nz))
+    g = gx[pts[:, 0]] * gy[pts[:, 1]] * gz[pts[:, 2]]
     an = _Gathered(W.shape, a_tab)
-    ap = _Gathered(W.shape, {tuple(int(i) for i in (z, y, x)): Ac[i_] - Vc[i_]
+    ap = _Gathered(W.shape, {tuple(int(i) for i in (z, y, x)): (Ac[i_] - Vc[i_]) / g[i_]
                              for i_, (x, y, z) in enumerate(pts)})
     vv = _Gathered(W.shape, {tuple(int(i) for i in (z, y, x)): vc[i_] for i_, (x, y, z) in enumerate(pts)})
-    a_new = oracle.step_at(pts, an, ap, vv, W.h, dt, src=W.src, s_n=float(wav[0]))
-    v_new = a_new - Ac
+    a_new = oracle.step_at(pts, an, ap, vv, W.h, dt, src=W.src, s_n=float(wav[0]), sponge_width=W.sponge_width,
+                           sponge_alpha=W.sponge_alpha)
+    v_new = a_new - g * Ac
     hx, hy, hz = (W.h,) * 3 if np.isscalar(W.h) else W.h
     c = oracle.second_derivative_weights(4)
     sten = np.zeros(len(pts))
@@ -336,12 +345,12 @@ def test_full_size_1024_one_step_encoding(fmt, bits):
     q = np.zeros(len(pts))
     q[-1] = dt * dt * float(wav[0]) / (hx * hy * hz)
     M = (dt * vc) ** 2
-    terms_v = np.abs(Vc) + M * sten + np.abs(q)
-    terms_a = np.abs(Ac) + terms_v
+    terms_v = g * (np.abs(Vc) + M * sten + np.abs(q))
+    terms_a = g * np.abs(Ac) + terms_v
     gamma = growth_bound_gamma(v_hi, W.h, dt)
     bv = v_max + gamma * a_max + abs(q[-1])
-    for name, got, exact, e, terms in (("A", got_a, a_new, scale_exponent(a_max + bv), terms_a),
-                                       ("V", got_v, v_new, scale_exponent(bv), terms_v)):
+    for fld, got, exact, e, terms in (("A", got_a, a_new, scale_exponent(a_max + bv), terms_a),
+                                      ("V", got_v, v_new, scale_exponent(bv), terms_v)):
         emu = quantize(exact * 2.0 ** e, fmt) * 2.0 ** -e
         scaled = got * 2.0 ** e
         assert np.array_equal(quantize(scaled, fmt), scaled)  # values on the format's grid at that exponent
@@ -352,7 +361,7 @@ def test_full_size_1024_one_step_encoding(fmt, bits):
         slack = 16 * 2.0 ** -24 * terms * 2.0 ** e
         dist = np.abs(got - emu) * 2.0 ** e
         worst = (dist / (step + slack))[live].max()
-        _say(f"{fmt} m{bits} {name}: exponent {e}, {diff.sum()} of {live.sum()} live sampled values differ, "
+        _say(f"{fmt} m{bits} {fld}: exponent {e}, {diff.sum()} of {live.sum()} live sampled values differ, "
              f"worst {worst:.2f} of (ulp + float32 evaluation bound)")
         assert live.sum() > 1000
         assert frac <= 1e-2 and worst <= 1.0 + 1e-9

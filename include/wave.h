@@ -241,8 +241,11 @@ int wave_read_field(wave_t w, int32_t which, float *out_dev);
  * g A^{n-1}, each rounded to nearest even at the power-of-two scale the step
  * rule gives for the field's maximum (stored magnitudes below 2^14), with the
  * field's scale and maximum records set as a step would leave them.  Other
- * values of which: WAVE_EINVAL.  The step counter is unchanged.  Enqueued on
- * the context's stream; in_dev must stay valid until the stream reaches it. */
+ * values of which: WAVE_EINVAL.  The step counter is unchanged.  Non-finite
+ * inputs are stored as given (the scale then falls back to 2^0 or its
+ * clamp), and wave_sync_status reports them as for a run that diverged.
+ * Enqueued on the context's stream; in_dev must stay valid until the stream
+ * reaches it. */
 int wave_write_field(wave_t w, int32_t which, const float *in_dev);
 
 /* Host copy of the step counter n (steps since the last reset). */

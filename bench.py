@@ -198,12 +198,13 @@ def stream_ceiling(dev, n: int, reps: int = 20) -> dict:
     return out
 
 
-def size_probe(n: int, steps: int = 30) -> dict:
+def size_probe(n: int, steps: int = 30, tilings=()) -> dict:
     """One grid size N^3 (smooth random model, Dirichlet, a line of
     receivers): the HIP stream ceiling of that size, then the float32 step
     kernel in its tuned configuration; its algorithmic GB/s (16 B per point)
     against the ceiling.  Run under rocprofv3 counters, it gives the bytes
-    each kernel moves per launch."""
+    each kernel moves per launch.  tilings: (variant, zchunk) pairs also
+    timed with tuning off (20 steps, best of two runs each)."""
     import torch
 
     from paper_2404_04441_amd import Solver
@@ -225,6 +226,19 @@ def size_probe(n: int, steps: int = 30) -> dict:
     s.close()
     r["frac_of_stream_3r1w"] = round(r["gb_per_s"] / out["ceiling"]["stream_3r1w_gb_per_s"], 4)
     out["step_f32"] = r
+    fixed = []
+    for var, zc in tilings:
+        s = Solver(v, W.h, W.dt, src=(n // 2, n // 2, n // 2), rec=rec, variant=var, zchunk=zc, tune=False)
+        s.run(3, wav, tr)
+        best = min((kernel_rate(s, 20, wav, tr, n ** 3, BYTES_PER_POINT["f32"]) for _ in range(2)),
+                   key=lambda x: x["kernel_ms"])
+        best["tiling"] = s.tiling()
+        s.close()
+        best["frac_of_stream_3r1w"] = round(best["gb_per_s"] / out["ceiling"]["stream_3r1w_gb_per_s"], 4)
+        print(f"[bench] size probe {n}^3 variant {var} z-chunk {zc}: {best}", file=sys.stderr, flush=True)
+        fixed.append(best)
+    if fixed:
+        out["fixed_tilings"] = fixed
     print(f"[bench] size probe {n}^3: {out}", file=sys.stderr, flush=True)
     return out
 
@@ -617,6 +631,8 @@ def main():
                     help="run only the 256^3 x 800 gradient leg and print its JSON")
     ap.add_argument("--size-probe", type=int, default=0,
                     help="run only the N^3 size probe (HIP stream ceiling + tuned float32 step) and print its JSON")
+    ap.add_argument("--probe-tilings", default="",
+                    help="with --size-probe: also time these fixed tilings, 'variant:zchunk,...' (tuning off)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -639,7 +655,8 @@ def main():
     if args.size_probe:
         if args.copy_calibration:
             copy_calibration(torch.device("cuda:0"))
-        print(json.dumps({"size_probe": size_probe(args.size_probe)}), flush=True)
+        pairs = [tuple(int(x) for x in t.split(":")) for t in args.probe_tilings.split(",") if t]
+        print(json.dumps({"size_probe": size_probe(args.size_probe, tilings=pairs)}), flush=True)
         return
     if args.precision_only:
         if args.copy_calibration:

@@ -156,6 +156,7 @@ def _probe_lib():
         vp, sz = ctypes.c_void_p, ctypes.c_size_t
         L.probe_stream_3r1w.argtypes = [vp, vp, vp, vp, sz, vp]
         L.probe_copy.argtypes = [vp, vp, sz, vp]
+        L.probe_stream_16bit.argtypes = [vp, vp, vp, vp, vp, sz, ctypes.c_int, vp]
         _PROBE = L
     return _PROBE
 
@@ -259,6 +260,51 @@ def copy_calibration(dev) -> None:
     torch.cuda.empty_cache()
 
 
+def stream16_ceiling(dev, n: int, reps: int = 20) -> dict:
+    """The 16-bit storage step's traffic shape as a plain HIP stream over n
+    nodes: A and V read at 2 B, m at 4 B (or 2 B as 16-bit codes), A' and V'
+    written at 2 B, four nodes per lane, the step's cache policies and XCD
+    remap.  Rates in nodes per second, so each 16-bit form can be set against
+    the stream of its own access shape."""
+    import torch
+
+    n = n // 4 * 4
+    lib = _probe_lib()
+    a = torch.zeros(n, dtype=torch.int16, device=dev)
+    v = torch.zeros_like(a)
+    ao = torch.empty_like(a)
+    vo = torch.empty_like(a)
+    m = torch.zeros(n, dtype=torch.float32, device=dev)
+    st = torch.cuda.current_stream(dev)
+    out = {"kernel": "libwave_probe stream_16bit", "nodes": n}
+    for m16, key, bpp in ((0, "m_f32", 12), (1, "m_16bit", 10)):
+        def fn():
+            return lib.probe_stream_16bit(a.data_ptr(), v.data_ptr(), m.data_ptr(), ao.data_ptr(), vo.data_ptr(), n,
+                                          m16, st.cuda_stream)
+        for _ in range(3):
+            assert fn() == 0
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[key] = {"ms": round(ms, 4), "gpts_per_s": round(n / ms / 1e6, 2), "gb_per_s": round(bpp * n / ms / 1e6, 1)}
+    del a, v, ao, vo, m
+    torch.cuda.empty_cache()
+    return out
+
+
+def _frac_of_stream16(out: dict, ceiling: dict) -> None:
+    """Each 16-bit form's rate against the stream of its own access shape."""
+    for form, r in out.items():
+        if isinstance(r, dict) and "gpts_per_s" in r and form != "f32":
+            ref = ceiling["m_16bit" if form.endswith("_m16") else "m_f32"]["gpts_per_s"]
+            r["frac_of_stream_16bit"] = round(r["gpts_per_s"] / ref, 4)
+
+
 def kernel_rate(s, nt, wav, traces, npts, bpp, ref_bpp=None):
     """Average step-kernel time (events on the solver's stream) -> Gpts/s, GB/s
     and the fraction of 8 TB/s at bpp algorithmic bytes per point (and at
@@ -302,6 +348,8 @@ def storage_forms_leg(W, vel_dev, nt: int) -> dict:
         out[fmt] = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT[fmt], SURVEY_16BIT_BYTES)
         out[fmt]["tiling"] = s.tiling()
         s.close()
+    out["stream_16bit"] = stream16_ceiling(vel_dev.device, W.npts)
+    _frac_of_stream16(out, out["stream_16bit"])
     return out
 
 
@@ -365,6 +413,8 @@ def precision_leg(nt: int = 500) -> dict:
     del vel
     torch.cuda.empty_cache()
     out["stream_ceiling"] = stream_ceiling(dev, W.npts)  # HIP streams of the 1024^3 size
+    out["stream_16bit"] = stream16_ceiling(dev, W.npts)
+    _frac_of_stream16(out, out["stream_16bit"])
     return out
 
 

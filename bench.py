@@ -264,35 +264,37 @@ def stream16_ceiling(dev, n: int, reps: int = 20) -> dict:
     """The 16-bit storage step's traffic shape as a plain HIP stream over n
     nodes: A and V read at 2 B, m at 4 B (or 2 B as 16-bit codes), A' and V'
     written at 2 B, four nodes per lane, the step's cache policies and XCD
-    remap.  Rates in nodes per second, so each 16-bit form can be set against
-    the stream of its own access shape."""
+    remap.  As in a run of steps, A' goes to the other A buffer and becomes
+    the next launch's input, and V is updated in place: a launch never reads
+    the A it just read again (at 512^3 an A field is as large as the 256 MB
+    last-level cache).  Rates in nodes per second, so each 16-bit form can be
+    set against the stream of its own access shape."""
     import torch
 
     n = n // 4 * 4
     lib = _probe_lib()
-    a = torch.zeros(n, dtype=torch.int16, device=dev)
-    v = torch.zeros_like(a)
-    ao = torch.empty_like(a)
-    vo = torch.empty_like(a)
+    bufs = [torch.zeros(n, dtype=torch.int16, device=dev) for _ in range(2)]
+    v = torch.zeros_like(bufs[0])
     m = torch.zeros(n, dtype=torch.float32, device=dev)
     st = torch.cuda.current_stream(dev)
     out = {"kernel": "libwave_probe stream_16bit", "nodes": n}
     for m16, key, bpp in ((0, "m_f32", 12), (1, "m_16bit", 10)):
-        def fn():
-            return lib.probe_stream_16bit(a.data_ptr(), v.data_ptr(), m.data_ptr(), ao.data_ptr(), vo.data_ptr(), n,
+        def fn(k):
+            a, ao = bufs[k % 2], bufs[(k + 1) % 2]
+            return lib.probe_stream_16bit(a.data_ptr(), v.data_ptr(), m.data_ptr(), ao.data_ptr(), v.data_ptr(), n,
                                           m16, st.cuda_stream)
-        for _ in range(3):
-            assert fn() == 0
+        for k in range(3):
+            assert fn(k) == 0
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(st)
-        for _ in range(reps):
-            fn()
+        for k in range(reps):
+            fn(k + 1)
         e1.record(st)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         out[key] = {"ms": round(ms, 4), "gpts_per_s": round(n / ms / 1e6, 2), "gb_per_s": round(bpp * n / ms / 1e6, 1)}
-    del a, v, ao, vo, m
+    del bufs, v, m
     torch.cuda.empty_cache()
     return out
 
@@ -675,6 +677,8 @@ def main():
                     help="run only the 1024^3 kernel study (3D gmem/smem vs 2.5D shapes) and print its JSON")
     ap.add_argument("--cpml-only", action="store_true",
                     help="run only the 512^3 CPML leg (fused and unfused shapes) and print its JSON")
+    ap.add_argument("--forms-only", action="store_true",
+                    help="run only the 512^3 16-bit storage forms (and their stream probe) and print JSON")
     ap.add_argument("--precision-only", action="store_true",
                     help="run only the 1024^3 storage forms (float32, 16-bit, 16-bit with 16-bit m) and print JSON")
     ap.add_argument("--gradient-only", action="store_true",
@@ -731,6 +735,12 @@ def main():
             copy_calibration(dev)
         v_dev = torch.from_numpy(W.velocity()).to(dev)
         print(json.dumps({"cpml_512": cpml_leg(W, v_dev, min(args.nt or W.nt, 200))}), flush=True)
+        return
+    if args.forms_only:
+        if args.copy_calibration:
+            copy_calibration(dev)
+        v_dev = torch.from_numpy(W.velocity()).to(dev)
+        print(json.dumps({"forms_512": storage_forms_leg(W, v_dev, min(args.nt or W.nt, 200))}), flush=True)
         return
     nt = args.nt or W.nt
     print(f"[bench] building {W.name} inputs", file=sys.stderr, flush=True)

@@ -82,11 +82,11 @@ typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 // one group of four nodes per lane; A with the regular policy, the rest
-// nontemporal, as the step kernel
+// nontemporal, as the step kernel; vo may be v (updated in place, as V is)
 template <bool M16>
-__global__ void __launch_bounds__(kThreads) stream_16bit(const u2 *__restrict__ a, const u2 *__restrict__ v,
-                                                          const void *__restrict__ m, u2 *__restrict__ ao,
-                                                          u2 *__restrict__ vo, size_t ng) {
+__global__ void __launch_bounds__(kThreads) stream_16bit(const u2 *__restrict__ a, const u2 *v,
+                                                          const void *__restrict__ m, u2 *__restrict__ ao, u2 *vo,
+                                                          size_t ng) {
   const size_t i = block_of() * kThreads + threadIdx.x;
   if (i >= ng) return;
   const u2 xa = a[i];
@@ -122,7 +122,7 @@ int probe_stream_3r1w(const float *a, const float *b, const float *c, float *d, 
 }
 
 // n nodes (a multiple of 4): a, v, ao, vo hold n 16-bit values, m n floats
-// (m16 == 0) or n 16-bit codes (m16 != 0), all 16-byte aligned
+// (m16 == 0) or n 16-bit codes (m16 != 0), all 16-byte aligned; vo may be v
 int probe_stream_16bit(const void *a, const void *v, const void *m, void *ao, void *vo, size_t n, int m16,
                        void *stream) {
   if (n % 4 || !a || !v || !m || !ao || !vo) return static_cast<int>(hipErrorInvalidValue);

@@ -77,3 +77,8 @@ def test_probe_outputs(probe):
         assert np.array_equal(ao[:n].view(np.uint32).reshape(-1, 2), wa ^ wm)
         assert np.array_equal(vo[:n].view(np.uint32).reshape(-1, 2), wv + wm)  # wrapping add per word
         assert np.all(ao[n:] == 3) and np.all(vo[n:] == 3)
+        # V updated in place, as the benchmark runs it
+        assert probe.probe_stream_16bit(ga.data_ptr(), gv.data_ptr(), gm.data_ptr(), gao.data_ptr(), gv.data_ptr(),
+                                        n, m16, st) == 0
+        torch.cuda.synchronize()
+        assert np.array_equal(gv.cpu().numpy().view(np.uint16).view(np.uint32).reshape(-1, 2), wv + wm)

@@ -37,14 +37,16 @@ static_assert(sizeof(StepState) == 128, "state block layout");
 // with c0 = -2 sum_m c_m this is the same operator, but no large centre term
 // is summed against its neighbours (in float32 that cancellation dominated
 // the rounding error of a long run; see the tolerance notes in the tests).
-// The one exception is the step with the CPML x terms fused in, which sums
-// each axis from its centre weight k0a (see step_kernel).
+// Two kernels sum the operator from its centre weight instead (Eq. 1 as
+// written): the step with the CPML x terms fused in, per axis from k0a, and
+// the f16 step with 16-bit m, from k0 (see step_kernel).
 struct Coef {
   float kx[4];     // c_m / dx^2, m = 1..4
   float ky[4];
   float kz[4];
   float k0a[3];    // c0 / h_a^2 per axis: the fused CPML step sums each axis' second derivative
                    // from its centre term (see step_kernel)
+  float k0;        // c0 (1/dx^2 + 1/dy^2 + 1/dz^2): the centre weight of the whole operator
 };
 
 // Receivers forming a regular box, listed x fastest then y then z:

@@ -837,6 +837,7 @@ int create_ctx(const wave_params *p, const float *vel_dev, void *ws_dev, size_t 
   w->c.k0a[0] = static_cast<float>(kC[0] * ix2);
   w->c.k0a[1] = static_cast<float>(kC[0] * iy2);
   w->c.k0a[2] = static_cast<float>(kC[0] * iz2);
+  w->c.k0 = static_cast<float>(kC[0] * (ix2 + iy2 + iz2));
   for (int m = 1; m <= 4; ++m) {
     w->c.kx[m - 1] = static_cast<float>(kC[m] * ix2);
     w->c.ky[m - 1] = static_cast<float>(kC[m] * iy2);

@@ -335,13 +335,21 @@ def test_full_size_one_step_encoding(name, fmt, bits):
     v_new = a_new - g * Ac
     hx, hy, hz = (W.h,) * 3 if np.isscalar(W.h) else W.h
     c = oracle.second_derivative_weights(4)
+    # the size of the terms the kernel's float32 Laplacian sums: centred
+    # differences, or (f16 with 16-bit m) the centre term and the neighbour
+    # values themselves, about 25 roundings (one per operation) instead of 16
+    sum_form = fmt == "f16" and bits == 16
     sten = np.zeros(len(pts))
     for i_, (x, y, z) in enumerate(pts):
         ctr = an[z, y, x]
+        ref = 0.0 if sum_form else ctr
+        if sum_form:
+            sten[i_] = abs(c[0]) * (hx ** -2 + hy ** -2 + hz ** -2) * abs(ctr)
         for (dx, dy, dz), ha in (((1, 0, 0), hx), ((0, 1, 0), hy), ((0, 0, 1), hz)):
             for m_ in range(1, 5):
-                sten[i_] += abs(c[m_]) / ha ** 2 * (abs(an[z + m_ * dz, y + m_ * dy, x + m_ * dx] - ctr)
-                                                    + abs(an[z - m_ * dz, y - m_ * dy, x - m_ * dx] - ctr))
+                sten[i_] += abs(c[m_]) / ha ** 2 * (abs(an[z + m_ * dz, y + m_ * dy, x + m_ * dx] - ref)
+                                                    + abs(an[z - m_ * dz, y - m_ * dy, x - m_ * dx] - ref))
+    nround = 32 if sum_form else 16
     q = np.zeros(len(pts))
     q[-1] = dt * dt * float(wav[0]) / (hx * hy * hz)
     M = (dt * vc) ** 2
@@ -358,7 +366,7 @@ def test_full_size_one_step_encoding(name, fmt, bits):
         diff = (got != emu) & live
         frac = diff.sum() / live.sum()
         step = np.maximum(ULP[fmt] * np.abs(emu * 2.0 ** e), TINY[fmt])
-        slack = 16 * 2.0 ** -24 * terms * 2.0 ** e
+        slack = nround * 2.0 ** -24 * terms * 2.0 ** e
         dist = np.abs(got - emu) * 2.0 ** e
         worst = (dist / (step + slack))[live].max()
         _say(f"{fmt} m{bits} {fld}: exponent {e}, {diff.sum()} of {live.sum()} live sampled values differ, "

@@ -384,9 +384,11 @@ def cpml_leg(W, vel_dev, nt: int) -> dict:
                    variant=variant)
         s.run(10, wav, traces)
         r = kernel_rate(s, nt, wav, traces, W.npts, BYTES_PER_POINT["f32"])
+        tiling = s.tiling()
         s.close()
         out[name] = {"step_ms": r["kernel_ms"], "gpts_per_s": r["gpts_per_s"], "roofline_frac": r["roofline_frac"],
-                     "roofline_frac_cpml": round(cpml_bytes / (r["kernel_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+                     "roofline_frac_cpml": round(cpml_bytes / (r["kernel_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                     "tiling": tiling}
     return out
 
 

@@ -85,8 +85,8 @@ typedef struct {
                                 0 = automatic (the measured-best 2.5D shape for the storage type
                                 and nx).  WAVE_EINVAL: 2 or 4 x nodes per lane with nx not divisible
                                 by that; a 3D-blocked family with 16-bit storage or adjoint */
-  int32_t zchunk;            /* z-planes per workgroup, rounded up to a multiple of 9 and capped so a
-                                workgroup's buffers span < 2 GiB; 0 = chosen from the grid size */
+  int32_t zchunk;            /* z-planes per workgroup (any length; capped so a workgroup's buffers
+                                span < 2 GiB); 0 = chosen from the grid size */
   int32_t graph_steps;       /* >0: replay steps from a captured HIP graph of this many steps */
   int32_t tune;              /* 1 (the default) with variant = 0 and zchunk = 0: wave_create
                                 times candidate configurations for a few steps on the fresh

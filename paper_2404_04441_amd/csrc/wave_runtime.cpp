@@ -267,27 +267,27 @@ Tiling make_tiling(const wave_params *p, int variant) {
   t.tiles_x = (nx + TX - 1) / TX;
   t.tiles_y = (ny + TY - 1) / TY;
   int zc = p->zchunk;
-  if (zc > 0) zc = (zc + 8) / 9 * 9;  // the kernel advances nine planes per trip
   if (zc <= 0) {
-    // as many long-lived workgroups as fit on the 256 CUs at once: long
-    // z-chunks re-read fewer overlap planes and keep the prefetch pipeline full
+    // as many long-lived workgroups as fit on the 256 CUs at once, in equal
+    // z-chunks: long chunks re-read fewer overlap planes and keep the
+    // prefetch pipeline full
     const int per_plane = t.tiles_x * t.tiles_y;
     const int want = 256 * step_blocks_per_cu(p->storage, variant, p->cpml_width > 0);
     const int chunks = std::max(1, (want + per_plane / 2) / per_plane);
     zc = std::max(18, (nz + chunks - 1) / chunks);
-    zc = (zc + 8) / 9 * 9;
   }
-  // a workgroup's buffer resources span its z-chunk, R halo planes below and
-  // kMaxPD + R prefetch and halo planes above; every span (float32 fields)
-  // must stay below 2^31 bytes.  With at most 2^24 nodes per plane this
-  // leaves at least one nine-plane trip.
+  // a workgroup's buffer resources span its z-chunk rounded up to whole
+  // nine-plane trips, R halo planes below and kMaxPD + R prefetch and halo
+  // planes above; every span (float32 fields) must stay below 2^31 bytes.
+  // With at most 2^24 nodes per plane this leaves at least one trip.
   const int64_t plane_f = 4 * static_cast<int64_t>(nx) * ny;
   const int zc_max = (static_cast<int>(((int64_t(1) << 31) - 1) / plane_f) - (2 * kRadius + kMaxPD)) / 9 * 9;
   if (zc > zc_max) {  // equal chunks that fit
     const int k = (nz + zc_max - 1) / zc_max;
-    zc = ((nz + k - 1) / k + 8) / 9 * 9;
-    if (zc > zc_max) zc = zc_max;
+    zc = std::min((nz + k - 1) / k, zc_max);
   }
+  // the fused CPML step runs whole nine-plane trips (no skip branch)
+  if (p->cpml_width > 0 && variant_fuses_cpml(variant)) zc = std::min((zc + 8) / 9 * 9, zc_max);
   t.zchunk = zc;
   t.nchunks = (nz + zc - 1) / zc;
   t.total_tiles = t.tiles_x * t.tiles_y * t.nchunks;

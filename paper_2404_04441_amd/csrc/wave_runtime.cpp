@@ -266,22 +266,34 @@ Tiling make_tiling(const wave_params *p, int variant) {
   const int TX = kTileX * v.vec;
   t.tiles_x = (nx + TX - 1) / TX;
   t.tiles_y = (ny + TY - 1) / TY;
-  int zc = p->zchunk;
-  if (zc <= 0) {
-    // as many long-lived workgroups as fit on the 256 CUs at once, in equal
-    // z-chunks: long chunks re-read fewer overlap planes and keep the
-    // prefetch pipeline full
-    const int per_plane = t.tiles_x * t.tiles_y;
-    const int want = 256 * step_blocks_per_cu(p->storage, variant, p->cpml_width > 0);
-    const int chunks = std::max(1, (want + per_plane / 2) / per_plane);
-    zc = std::max(18, (nz + chunks - 1) / chunks);
-  }
   // a workgroup's buffer resources span its z-chunk rounded up to whole
   // nine-plane trips, R halo planes below and kMaxPD + R prefetch and halo
   // planes above; every span (float32 fields) must stay below 2^31 bytes.
   // With at most 2^24 nodes per plane this leaves at least one trip.
   const int64_t plane_f = 4 * static_cast<int64_t>(nx) * ny;
   const int zc_max = (static_cast<int>(((int64_t(1) << 31) - 1) / plane_f) - (2 * kRadius + kMaxPD)) / 9 * 9;
+  int zc = p->zchunk;
+  if (zc <= 0) {
+    // k equal z-chunks, k minimising the launch time in the model
+    // (rounds of workgroups over the 256 CUs) x (planes per chunk + 3): the
+    // 3 stands for a chunk's overlap planes and pipeline fill, so long
+    // chunks win unless more of them fill the CUs' last round.  Chunks keep
+    // at least 18 planes and fit the resource span.
+    const int64_t per_plane = static_cast<int64_t>(t.tiles_x) * t.tiles_y;
+    const int64_t cap = 256 * static_cast<int64_t>(step_blocks_per_cu(p->storage, variant, p->cpml_width > 0));
+    const int k_min = (nz + zc_max - 1) / zc_max;
+    int best_k = k_min;
+    int64_t best_cost = -1;
+    for (int k = k_min; k == k_min || (nz + k - 1) / k >= 18; ++k) {
+      const int64_t rounds = (per_plane * k + cap - 1) / cap;
+      const int64_t cost = rounds * ((nz + k - 1) / k + 3);
+      if (best_cost < 0 || cost < best_cost) {
+        best_cost = cost;
+        best_k = k;
+      }
+    }
+    zc = (nz + best_k - 1) / best_k;
+  }
   if (zc > zc_max) {  // equal chunks that fit
     const int k = (nz + zc_max - 1) / zc_max;
     zc = std::min((nz + k - 1) / k, zc_max);

@@ -665,10 +665,12 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
   // y neighbours from this lane's own rows when they lie in the strip, else
   // from the LDS rows above and below.
   // CP: also the per-axis parts lax[a] (centre weight c_0 / h_a^2 each), and
-  // lap = (lax[0] + lax[1]) + lax[2].  kSumForm: k0 u + sum k_m (u(+m) + u(-m)).
+  // lap = (lax[0] + lax[1]) + lax[2].  sum_form (a compile-time flag): k0 u +
+  // sum k_m (u(+m) + u(-m)) instead of the centred differences.
   auto laplacian = [&](const float (&Q)[kQ][RY][VEC], const float *Lp, int cs, int s0, int j, float *lap,
-                       const float (&Xp)[SEMI ? kQ : 1][RY][VEC], float (&lax)[3][VEC])
+                       const float (&Xp)[SEMI ? kQ : 1][RY][VEC], float (&lax)[3][VEC], auto sum_form)
                        __attribute__((always_inline)) {
+    constexpr bool kSum = decltype(sum_form)::value;
     const float *row = Lp + (R + w * RY + j) * LW + VEC * lane;  // window start: column x - R
     float win[VEC + 2 * R];
 #pragma unroll
@@ -676,7 +678,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
       if (VEC > 1 || k != R) lds_get<VEC>(row + VEC * k, win + VEC * k);
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
-      lap[i] = kSumForm ? a.c.k0 * Q[cs][j][i] : 0.f;
+      lap[i] = kSum ? a.c.k0 * Q[cs][j][i] : 0.f;
       if constexpr (CP) {  // per axis, from the centre term (the sum form; see below)
 #pragma unroll
         for (int d = 0; d < 3; ++d) lax[d][i] = a.c.k0a[d] * Q[cs][j][i];
@@ -713,7 +715,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
           lax[0][i] = fmaf(a.c.kx[m - 1], win[R + i + m] + win[R + i - m], lax[0][i]);
           lax[1][i] = fmaf(a.c.ky[m - 1], yp[i] + ym[i], lax[1][i]);
           lax[2][i] = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i] + Q[(s0 + R - m + kQ) % kQ][j][i], lax[2][i]);
-        } else if constexpr (kSumForm) {
+        } else if constexpr (kSum) {
           lap[i] = fmaf(a.c.kx[m - 1], win[R + i + m] + win[R + i - m], lap[i]);
           lap[i] = fmaf(a.c.ky[m - 1], yp[i] + ym[i], lap[i]);
           lap[i] = fmaf(a.c.kz[m - 1], Q[(s0 + R + m) % kQ][j][i] + Q[(s0 + R - m + kQ) % kQ][j][i], lap[i]);
@@ -832,7 +834,7 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
         float lap[VEC], lax[3][VEC];
-        laplacian(q, L, cslot, s, j, lap, X, lax);
+        laplacian(q, L, cslot, s, j, lap, X, lax, std::integral_constant<bool, kSumForm>{});
         if constexpr (CP) {  // x part of the CPML terms: D1_x psi_x + zeta_x, zeta_x updated
           const int yj = yb + j;
           float ext[VEC], zn[VEC];
@@ -902,8 +904,11 @@ __global__ void __launch_bounds__(64 * BY) step_kernel(StepArgs a) {
           rkeep[S != kF32 ? j : 0] = ra;
         }
         if constexpr (ADJ) {
+          // the imaging term L(A^k), only accumulated (no recurrence runs
+          // through it): summed from the centre weight, 25 instead of 48
+          // operations per node
           float lapF[VEC], im[VEC], laxF[3][VEC];
-          laplacian(qF, LF, cslot, s, j, lapF, X, laxF);
+          laplacian(qF, LF, cslot, s, j, lapF, X, laxF, std::integral_constant<bool, true>{});
 #pragma unroll
           for (int i = 0; i < VEC; ++i) im[i] = fmaf(q[cslot][j][i], lapF[i], ic[j][i]);
           st_words<NF, kNT>(row_put<kF32, VEC>(im), rI, vrow_f[j], sz0f);

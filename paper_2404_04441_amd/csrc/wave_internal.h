@@ -37,9 +37,10 @@ static_assert(sizeof(StepState) == 128, "state block layout");
 // with c0 = -2 sum_m c_m this is the same operator, but no large centre term
 // is summed against its neighbours (in float32 that cancellation dominated
 // the rounding error of a long run; see the tolerance notes in the tests).
-// Two kernels sum the operator from its centre weight instead (Eq. 1 as
-// written): the step with the CPML x terms fused in, per axis from k0a, and
-// the f16 step with 16-bit m, from k0 (see step_kernel).
+// Some terms sum the operator from its centre weight instead (Eq. 1 as
+// written): the step with the CPML x terms fused in, per axis from k0a; the
+// f16 step with 16-bit m and the adjoint step's imaging term L(A^k), from k0
+// (see step_kernel).
 struct Coef {
   float kx[4];     // c_m / dx^2, m = 1..4
   float ky[4];

@@ -469,21 +469,24 @@ def kernel_study_leg(nt: int = 20) -> dict:
         print(f"[bench] kernel study {name}: {r}", file=sys.stderr, flush=True)
     del vel
     torch.cuda.empty_cache()
-    sweep, tuned = {}, {}
-    for n in (128, 256, 384, 512, 640, 768, 896, 1024):
+    sweep, tuned, tilings = {}, {}, {}
+    for n in (96, 128, 192, 256, 320, 384, 512, 640, 768, 896, 1024):
         v_n = smooth_random_torch((n, n, n), seed=3, device=dev)
         rec = line_receivers(n, n // 2, 4)
         tr = torch.empty((50, len(rec)), dtype=torch.float32, device=dev)
         steps = 50 if n <= 512 else nt
-        for tune, dst in ((False, sweep), (True, tuned)):
+        tilings[str(n)] = {}
+        for tune, dst, key in ((False, sweep, "fixed"), (True, tuned, "tuned")):
             s = Solver(v_n, W.h, W.dt, src=(n // 2, n // 2, n // 2), rec=rec, tune=tune)
             s.run(3, wav, tr)
             dst[str(n)] = kernel_rate(s, steps, wav, tr, n ** 3, BYTES_PER_POINT["f32"])["gpts_per_s"]
+            tilings[str(n)][key] = s.tiling()
             s.close()
         del v_n
         torch.cuda.empty_cache()
     out["grid_sweep_gpts_per_s"] = sweep
     out["grid_sweep_tuned_gpts_per_s"] = tuned
+    out["grid_sweep_tilings"] = tilings
     print(f"[bench] grid sweep: {sweep} tuned: {tuned}", file=sys.stderr, flush=True)
     return out
 
